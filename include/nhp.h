@@ -1,0 +1,178 @@
+/*
+ * nhp.h -- C ABI of the MI355X kernel-style N-turn nonholonomic planner.
+ *
+ * The method is Nister, Soundararajan, Wang, Sane, "Nonholonomic Motion
+ * Planning as Efficient as Piano Mover's" (arXiv 2306.01301).  The pipeline
+ * of Sec. XI maps onto these calls:
+ *   plan_create    graph and tables (Sec. V.C-D, eqs. 11-31)
+ *   render_cspace  obstacle rendering (Sec. VI)
+ *   sweep_n_turns  N cycles of the six maneuver kernels (Sec. VIII.B,
+ *                  Insert 1; cycle order of Sec. XVI.A)
+ *   extract_path   goal search (Sec. IX) and back-tracking (Sec. X, eq. 32)
+ *
+ * Conventions shared by every entry point:
+ *   - Status: every function returning int returns NHP_OK (0) or a negative
+ *     nhp_status; plan_last_error() then gives a message (thread-local).
+ *     No C++ exception ever crosses this boundary.
+ *   - Pointers named d_* are device pointers (HIP global memory on the
+ *     plan's device); pointers named h_* are host pointers.  The library never
+ *     frees memory it did not allocate.
+ *   - Asynchrony: calls enqueue work on the plan's stream and return; only
+ *     extract_path and plan_get_tables synchronise with it.
+ *   - Volumes are laid out [theta][y][x] with x fastest: the pose (i, j, T)
+ *     is element (T * nx + j) * nx + i.  Values are uint32 costs in 1/1024
+ *     cell (NHP_INF = unreached); obstacle codes are uint8, 0..254 soft
+ *     (slowness (256 + 4 code) / 256), 255 hard.
+ *   - Concurrency: one plan must not be used from two threads at once;
+ *     different plans are independent and may run concurrently on different
+ *     streams.
+ */
+#ifndef NHP_H
+#define NHP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NHP_INF 0xFFFFFFFFu
+#define NHP_HARD 255u
+#define NHP_MAX_STEPS_DEVICE 4096u /* back-tracking steps kept on the device */
+
+typedef struct nhp_plan nhp_plan; /* opaque: tables, device state, stream */
+
+enum nhp_status {
+  NHP_OK = 0,
+  NHP_EINVAL = -1,   /* invalid argument or parameter */
+  NHP_ENOMEM = -2,   /* workspace too small or allocation failed */
+  NHP_EHIP = -3,     /* a HIP runtime call failed */
+  NHP_ESTART = -4,   /* the start pose is in collision */
+  NHP_EUNREACH = -5, /* no reached, collision-free pose in the goal window */
+  NHP_ECAP = -6,     /* the caller's step buffer is too small */
+  NHP_ESTATE = -7    /* call out of order (e.g. sweep before render) */
+};
+
+/* The six maneuvers (Sec. V: LEFT/STRAIGHT/RIGHT x FORWARD/BACKWARD), in the
+ * cycle order of Sec. XVI.A. */
+enum nhp_maneuver { NHP_LF = 0, NHP_SF = 1, NHP_RB = 2, NHP_RF = 3, NHP_SB = 4, NHP_LB = 5 };
+
+/* Problem parameters (Sec. IV-V).  Grid: nx x nx cells x ntheta headings,
+ * theta(T) = 2 pi T / ntheta; one-cell hard walls at i = 0 and j = 0 make
+ * the torus of Sec. V.C. */
+typedef struct nhp_params {
+  uint32_t nx;          /* cells per side; 16..1024, a multiple of 8 */
+  uint32_t ntheta;      /* heading planes; 8..1024, a multiple of 8 */
+  double turn_radius;   /* minimum turn radius R in cells, > 0 */
+  uint32_t ct_q10[6];   /* transition cost into each maneuver, 1/1024 cell */
+  uint32_t gear_q8[6];  /* edge-length multiplier per maneuver, 1/256 (256 = 1.0) */
+  uint8_t schedule[6];  /* maneuver order within a cycle (default LF SF RB RF SB LB) */
+  uint8_t n_schedule;   /* maneuvers per cycle, 1..6 (3 with LF SF RF = forward only) */
+  uint8_t half_cell;    /* 1: half-cell vertex positions (eqs. 13-16); 0: plain rounding */
+  uint8_t reserved[6];  /* zero */
+} nhp_params;
+
+/* One maneuver of an extracted plan: `steps` edges of `maneuver` from pose
+ * from_ijt to pose to_ijt, costing cost_q10 (its transition cost plus the
+ * weights of its edges). */
+typedef struct nhp_step {
+  uint8_t maneuver;
+  uint8_t pad[3];
+  uint32_t steps;
+  uint32_t from_ijt[3];
+  uint32_t to_ijt[3];
+  uint32_t cost_q10;
+} nhp_step;
+
+/* Device bytes a plan needs for `params` (value volume 4 B/pose, obstacle
+ * volume 1 B/pose, tables and scratch), or 0 when params are invalid. */
+size_t plan_workspace_bytes(const nhp_params* params);
+
+/* Builds the tables of eqs. (11)-(31) on the host and uploads them.
+ * d_workspace: caller-owned device memory of at least plan_workspace_bytes()
+ *   bytes, 256-byte aligned, alive until plan_destroy; NULL lets the library
+ *   allocate (and free) it.
+ * stream: hipStream_t the plan enqueues on (NULL = default stream).
+ * Errors: NHP_EINVAL (params), NHP_ENOMEM (workspace too small), NHP_EHIP. */
+int plan_create(const nhp_params* params, void* d_workspace, size_t workspace_bytes, void* stream,
+                nhp_plan** out);
+
+/* Frees the plan and any memory the library allocated for it.  Waits for the
+ * plan's stream first.  NULL is accepted. */
+int plan_destroy(nhp_plan* plan);
+
+/* Replaces the stream the plan enqueues on. */
+int plan_set_stream(nhp_plan* plan, void* stream);
+
+/* Obstacle rendering (Sec. VI): puts the hard walls into row 0 and column 0
+ * of the image, then for every heading plane takes the maximum code under the
+ * vehicle box, a sideways pass over offsets -half_width..half_width along the
+ * left normal followed by a lengthwise pass over -rear..front along the
+ * heading.  d_image: nx * nx codes, row-major (row = y), device memory, read
+ * only.  Box extents in cells from the rear axle, each 0..255.  Invalidates
+ * any value volume (the value memory serves as scratch).
+ * Errors: NHP_EINVAL, NHP_EHIP. */
+int render_cspace(nhp_plan* plan, const uint8_t* d_image, int32_t front, int32_t rear,
+                  int32_t half_width);
+
+/* Loads an obstacle volume (nx*nx*ntheta codes, device memory) in place of
+ * rendering; the walls at i = 0 and j = 0 are forced hard afterwards. */
+int plan_set_cspace(nhp_plan* plan, const uint8_t* d_cspace);
+
+/* Sets V = NHP_INF everywhere and V(start) = 0, then runs n_cycles cycles of
+ * the schedule, each maneuver kernel relaxing every pose once (Insert 1; turn
+ * curves are cyclic and closed exactly, straights start at the wall).
+ * Errors: NHP_ESTATE (no obstacle volume), NHP_EINVAL, NHP_ESTART (start in
+ * collision; checked on the host, which synchronises once), NHP_EHIP. */
+int sweep_n_turns(nhp_plan* plan, uint32_t si, uint32_t sj, uint32_t st, uint32_t n_cycles);
+
+/* Runs n_more_cycles further cycles on the current value volume without
+ * re-initialising it (sweep_n_turns(a) then sweep_resume(b) equals
+ * sweep_n_turns(a + b)).  Errors: NHP_ESTATE. */
+int sweep_resume(nhp_plan* plan, uint32_t n_more_cycles);
+
+/* One maneuver kernel (Insert 1 over every curve of `maneuver`) on the
+ * current value volume, whatever it holds.  Errors: NHP_ESTATE, NHP_EINVAL. */
+int sweep_one(nhp_plan* plan, uint32_t maneuver);
+
+/* Goal search (Sec. IX) then back-tracking (Sec. X, eq. 32), both on the
+ * device; only the plan crosses to the host.
+ * Goal window: poses within max-norm `radius` (0..31) of (gi, gj, gt), each
+ * coordinate modulo its dimension; in-collision and unreached poses are
+ * skipped; score = V + w_xy_q10 (|dx| + |dy|) + w_t_q10 |dT| (saturating);
+ * ties go to the smaller (|dx|+|dy|+|dT|, dT, dy, dx).
+ * Back-tracking: from the best pose, for every scheduled maneuver every pose
+ * p_k up its curve through the current pose is a candidate worth
+ * V(p_k) + ct + (edge weights from p_k to the current pose); the smallest
+ * (value, schedule position, k) becomes the current pose, until the start.
+ * h_steps: host array of `cap` steps, filled start -> goal; *n_steps gets the
+ * plan length (also on NHP_ECAP).  best_ijt (3 entries), goal_value_q10
+ * (V at the best pose) and score_q10 may be NULL.  Synchronises the stream.
+ * Errors: NHP_ESTATE (no sweep yet), NHP_EINVAL, NHP_EUNREACH, NHP_ECAP,
+ * NHP_EHIP. */
+int extract_path(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t radius,
+                 uint32_t w_xy_q10, uint32_t w_t_q10, nhp_step* h_steps, uint32_t cap,
+                 uint32_t* n_steps, uint32_t* best_ijt, uint32_t* goal_value_q10,
+                 uint32_t* score_q10);
+
+/* Device pointers of the plan's value and obstacle volumes (for parity
+ * checks and checkpoints; owned by the plan).  Either output may be NULL. */
+int plan_device_ptrs(const nhp_plan* plan, uint32_t** d_value, uint8_t** d_cspace);
+
+/* Copies the host tables out (each host array may be NULL):
+ *   beta[ntheta], psi[ntheta]            eq. (13); psi in half cells
+ *   family[ntheta], fwd_sign[ntheta]     eqs. (19), (24)
+ *   skew[ntheta * nx]                    B(y', T) of eq. (22), [T][y']
+ *   edge_len[6 * ntheta]                 edge length per maneuver and plane,
+ *                                        1/1024 cell, gear applied, [mu][T] */
+int plan_get_tables(const nhp_plan* plan, int32_t* beta, int32_t* psi, int32_t* family,
+                    int32_t* fwd_sign, int32_t* skew, uint32_t* edge_len);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* plan_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NHP_H */

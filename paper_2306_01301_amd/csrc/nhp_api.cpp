@@ -1,0 +1,377 @@
+// nhp_api.cpp -- the C ABI of include/nhp.h: plan lifetime, argument checks,
+// call order, workspace layout and the launch sequence of Sec. XI.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "nhp_internal.h"
+
+using nhp::DevPlan;
+using nhp::HostTables;
+
+struct nhp_plan {
+  nhp_params p{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  HostTables t;
+  DevPlan d{};
+  bool has_cspace = false;
+  bool has_value = false;
+  uint32_t start[3] = {0, 0, 0};
+  int front = -1, rear = -1, half_width = -1;  // box of the last render (taps cached)
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int ok() {
+  g_err[0] = 0;
+  return NHP_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(NHP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_CHECK(call, what)                 \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t V, B, turn_off, skew, edge_len, fwd, family, planes, taps, extract, total;
+};
+
+int check_params(const nhp_params* p) {
+  if (!p) return fail(NHP_EINVAL, "params is NULL");
+  if (p->nx < 16 || p->nx > 1024 || p->nx % 8 != 0)
+    return fail(NHP_EINVAL, "nx must be a multiple of 8 in [16, 1024] (got %u)", p->nx);
+  if (p->ntheta < 8 || p->ntheta > 1024 || p->ntheta % 8 != 0)
+    return fail(NHP_EINVAL, "ntheta must be a multiple of 8 in [8, 1024] (got %u)", p->ntheta);
+  if (!(p->turn_radius > 0.0) || p->turn_radius > 1e6) return fail(NHP_EINVAL, "turn_radius must be > 0");
+  if (p->n_schedule < 1 || p->n_schedule > 6) return fail(NHP_EINVAL, "n_schedule must be 1..6");
+  for (int k = 0; k < p->n_schedule; k++)
+    if (p->schedule[k] > 5) return fail(NHP_EINVAL, "schedule[%d] is not a maneuver", k);
+  if (p->half_cell > 1) return fail(NHP_EINVAL, "half_cell must be 0 or 1");
+  for (int mu = 0; mu < 6; mu++)
+    if (p->gear_q8[mu] == 0 || p->gear_q8[mu] > 4096) return fail(NHP_EINVAL, "gear_q8 must be 1..4096");
+  return NHP_OK;
+}
+
+Layout layout_of(const nhp_params& p) {
+  Layout l{};
+  const size_t NR = (size_t)p.nx * p.nx * p.ntheta;
+  size_t o = 0;
+  l.V = o;
+  o = align256(o + NR * 4);
+  l.B = o;
+  o = align256(o + NR);
+  l.turn_off = o;
+  o = align256(o + 4 * (size_t)p.ntheta * 4);
+  l.skew = o;
+  o = align256(o + (size_t)p.ntheta * p.nx * 2);
+  l.edge_len = o;
+  o = align256(o + 6 * (size_t)p.ntheta * 4);
+  l.fwd = o;
+  o = align256(o + (size_t)p.ntheta * 4);
+  l.family = o;
+  o = align256(o + (size_t)p.ntheta * 4);
+  l.planes = o;
+  o = align256(o + (size_t)p.ntheta * 4);
+  l.taps = o;
+  o = align256(o + (size_t)p.ntheta * 2 * nhp::kMaxTaps * 4);
+  l.extract = o;
+  o = align256(o + (nhp::kExHeader + (size_t)NHP_MAX_STEPS_DEVICE * nhp::kExStepWords) * 4);
+  l.total = o;
+  return l;
+}
+
+int check_plan(const nhp_plan* plan) {
+  if (!plan) return fail(NHP_EINVAL, "plan is NULL");
+  return NHP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* plan_last_error(void) { return g_err; }
+
+size_t plan_workspace_bytes(const nhp_params* params) {
+  if (check_params(params) != NHP_OK) return 0;
+  return layout_of(*params).total;
+}
+
+int plan_create(const nhp_params* params, void* d_workspace, size_t workspace_bytes, void* stream,
+                nhp_plan** out) {
+  if (!out) return fail(NHP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_params(params);
+  if (rc) return rc;
+  if (d_workspace && ((uintptr_t)d_workspace & 255)) return fail(NHP_EINVAL, "workspace must be 256-byte aligned");
+  const Layout l = layout_of(*params);
+  if (d_workspace && workspace_bytes < l.total)
+    return fail(NHP_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, l.total);
+
+  nhp_plan* plan = new (std::nothrow) nhp_plan();
+  if (!plan) return fail(NHP_ENOMEM, "out of host memory");
+  plan->p = *params;
+  plan->stream = reinterpret_cast<hipStream_t>(stream);
+  rc = nhp::build_tables(plan->p, plan->t);
+  if (rc) {
+    delete plan;
+    return fail(rc, "edge lengths out of range: every edge must be 1/1024..2048 cells (turn radius or gear)");
+  }
+  hipError_t e = hipGetDevice(&plan->device);
+  if (e != hipSuccess) {
+    delete plan;
+    return hip_fail(e, "hipGetDevice");
+  }
+  if (d_workspace) {
+    plan->ws = d_workspace;
+    plan->ws_bytes = workspace_bytes;
+  } else {
+    e = hipMalloc(&plan->ws, l.total);
+    if (e != hipSuccess) {
+      delete plan;
+      return fail(NHP_ENOMEM, "hipMalloc of %zu bytes failed: %s", l.total, hipGetErrorString(e));
+    }
+    plan->ws_bytes = l.total;
+    plan->own_ws = true;
+  }
+  char* base = reinterpret_cast<char*>(plan->ws);
+  DevPlan& d = plan->d;
+  d.nx = (int)params->nx;
+  d.nt = (int)params->ntheta;
+  d.V = reinterpret_cast<uint32_t*>(base + l.V);
+  d.B = reinterpret_cast<uint8_t*>(base + l.B);
+  d.turn_off = reinterpret_cast<int32_t*>(base + l.turn_off);
+  d.skew = reinterpret_cast<int16_t*>(base + l.skew);
+  d.edge_len = reinterpret_cast<uint32_t*>(base + l.edge_len);
+  d.fwd = reinterpret_cast<int32_t*>(base + l.fwd);
+  d.family = reinterpret_cast<int32_t*>(base + l.family);
+  d.planes = reinterpret_cast<int32_t*>(base + l.planes);
+  d.taps = reinterpret_cast<int32_t*>(base + l.taps);
+  d.extract = reinterpret_cast<uint32_t*>(base + l.extract);
+  d.n_planes_x = (int)plan->t.planes_x.size();
+  d.n_planes_y = (int)plan->t.planes_y.size();
+  for (int mu = 0; mu < 6; mu++) {
+    d.ct[mu] = params->ct_q10[mu];
+    d.turn_lq[mu] = plan->t.edge_len[(size_t)mu * params->ntheta];
+    d.schedule[mu] = params->schedule[mu];
+  }
+  d.n_schedule = params->n_schedule;
+
+  std::vector<int32_t> planes(plan->t.planes_x);
+  planes.insert(planes.end(), plan->t.planes_y.begin(), plan->t.planes_y.end());
+  const HostTables& t = plan->t;
+  struct Up {
+    void* dst;
+    const void* src;
+    size_t n;
+  } ups[] = {
+      {d.turn_off, t.turn_off.data(), t.turn_off.size() * 4}, {d.skew, t.skew16.data(), t.skew16.size() * 2},
+      {d.edge_len, t.edge_len.data(), t.edge_len.size() * 4}, {d.fwd, t.fwd.data(), t.fwd.size() * 4},
+      {d.family, t.family.data(), t.family.size() * 4},       {d.planes, planes.data(), planes.size() * 4},
+  };
+  for (const Up& u : ups) {
+    e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, plan->stream);
+    if (e == hipSuccess) continue;
+    plan_destroy(plan);
+    return hip_fail(e, "table upload");
+  }
+  // the host vectors above are pageable and `planes` is local: wait for the copies
+  e = hipStreamSynchronize(plan->stream);
+  if (e != hipSuccess) {
+    plan_destroy(plan);
+    return hip_fail(e, "hipStreamSynchronize");
+  }
+  *out = plan;
+  return ok();
+}
+
+int plan_destroy(nhp_plan* plan) {
+  if (!plan) return ok();
+  (void)hipStreamSynchronize(plan->stream);
+  if (plan->own_ws && plan->ws) (void)hipFree(plan->ws);
+  delete plan;
+  return ok();
+}
+
+int plan_set_stream(nhp_plan* plan, void* stream) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  plan->stream = reinterpret_cast<hipStream_t>(stream);
+  return ok();
+}
+
+int render_cspace(nhp_plan* plan, const uint8_t* d_image, int32_t front, int32_t rear, int32_t half_width) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!d_image) return fail(NHP_EINVAL, "image is NULL");
+  if (front < 0 || rear < 0 || half_width < 0 || front > 255 || rear > 255 || half_width > 255)
+    return fail(NHP_EINVAL, "box extents must be 0..255 cells");
+  const int n_side = 2 * half_width + 1, n_len = front + rear + 1;
+  if (front != plan->front || rear != plan->rear || half_width != plan->half_width) {
+    const int L = (int)plan->p.ntheta;
+    std::vector<int32_t> taps((size_t)L * 2 * nhp::kMaxTaps, 0);
+    for (int T = 0; T < L; T++)
+      nhp::render_taps_host(plan->p, plan->t, T, front, rear, half_width, &taps[(size_t)T * 2 * nhp::kMaxTaps],
+                            &taps[(size_t)T * 2 * nhp::kMaxTaps + nhp::kMaxTaps]);
+    HIP_CHECK(hipMemcpyAsync(plan->d.taps, taps.data(), taps.size() * 4, hipMemcpyHostToDevice, plan->stream),
+              "tap upload");
+    HIP_CHECK(hipStreamSynchronize(plan->stream), "tap upload");
+    plan->front = front;
+    plan->rear = rear;
+    plan->half_width = half_width;
+  }
+  HIP_CHECK(nhp::launch_render(plan->d, d_image, n_side, n_len, plan->stream), "render_cspace launch");
+  plan->has_cspace = true;
+  plan->has_value = false;
+  return ok();
+}
+
+int plan_set_cspace(nhp_plan* plan, const uint8_t* d_cspace) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!d_cspace) return fail(NHP_EINVAL, "cspace is NULL");
+  const size_t NR = (size_t)plan->p.nx * plan->p.nx * plan->p.ntheta;
+  HIP_CHECK(hipMemcpyAsync(plan->d.B, d_cspace, NR, hipMemcpyDeviceToDevice, plan->stream), "cspace copy");
+  HIP_CHECK(nhp::launch_force_walls(plan->d, plan->stream), "wall launch");
+  plan->has_cspace = true;
+  plan->has_value = false;
+  return ok();
+}
+
+static int run_cycles(nhp_plan* plan, uint32_t n_cycles) {
+  for (uint32_t n = 0; n < n_cycles; n++)
+    for (int k = 0; k < plan->p.n_schedule; k++)
+      HIP_CHECK(nhp::launch_sweep(plan->d, plan->p.schedule[k], plan->stream), "sweep launch");
+  return NHP_OK;
+}
+
+int sweep_n_turns(nhp_plan* plan, uint32_t si, uint32_t sj, uint32_t st, uint32_t n_cycles) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!plan->has_cspace) return fail(NHP_ESTATE, "sweep_n_turns before render_cspace/plan_set_cspace");
+  if (si >= plan->p.nx || sj >= plan->p.nx || st >= plan->p.ntheta) return fail(NHP_EINVAL, "start outside the grid");
+  const size_t s = ((size_t)st * plan->p.nx + sj) * plan->p.nx + si;
+  uint8_t code = 0;
+  HIP_CHECK(hipMemcpyAsync(&code, plan->d.B + s, 1, hipMemcpyDeviceToHost, plan->stream), "start check");
+  HIP_CHECK(hipStreamSynchronize(plan->stream), "start check");
+  if (code == NHP_HARD) return fail(NHP_ESTART, "start pose (%u, %u, %u) is in collision", si, sj, st);
+  HIP_CHECK(nhp::launch_init(plan->d, (uint32_t)s, plan->stream), "init launch");
+  plan->start[0] = si;
+  plan->start[1] = sj;
+  plan->start[2] = st;
+  plan->has_value = true;
+  return (rc = run_cycles(plan, n_cycles)) ? rc : ok();
+}
+
+int sweep_resume(nhp_plan* plan, uint32_t n_more_cycles) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!plan->has_value) return fail(NHP_ESTATE, "sweep_resume before sweep_n_turns");
+  return (rc = run_cycles(plan, n_more_cycles)) ? rc : ok();
+}
+
+int sweep_one(nhp_plan* plan, uint32_t maneuver) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!plan->has_cspace) return fail(NHP_ESTATE, "sweep_one before render_cspace/plan_set_cspace");
+  if (maneuver > 5) return fail(NHP_EINVAL, "maneuver must be 0..5");
+  HIP_CHECK(nhp::launch_sweep(plan->d, (int)maneuver, plan->stream), "sweep launch");
+  return ok();
+}
+
+int extract_path(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t radius, uint32_t w_xy_q10,
+                 uint32_t w_t_q10, nhp_step* h_steps, uint32_t cap, uint32_t* n_steps, uint32_t* best_ijt,
+                 uint32_t* goal_value_q10, uint32_t* score_q10) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!plan->has_value) return fail(NHP_ESTATE, "extract_path before sweep_n_turns");
+  if (gi >= plan->p.nx || gj >= plan->p.nx || gt >= plan->p.ntheta) return fail(NHP_EINVAL, "goal outside the grid");
+  if (radius > (uint32_t)nhp::kMaxRadius) return fail(NHP_EINVAL, "goal radius must be 0..%d", nhp::kMaxRadius);
+  if (cap > 0 && !h_steps) return fail(NHP_EINVAL, "h_steps is NULL");
+  HIP_CHECK(nhp::launch_extract(plan->d, plan->start[0], plan->start[1], plan->start[2], gi, gj, gt, (int)radius,
+                                w_xy_q10, w_t_q10, plan->stream),
+            "extract launch");
+  uint32_t head[nhp::kExHeader];
+  HIP_CHECK(hipMemcpyAsync(head, plan->d.extract, sizeof(head), hipMemcpyDeviceToHost, plan->stream), "extract copy");
+  HIP_CHECK(hipStreamSynchronize(plan->stream), "extract copy");
+  const uint32_t status = head[0], n = head[1];
+  if (n_steps) *n_steps = n;
+  if (status != 0 && status != (uint32_t)(-NHP_EUNREACH))
+    return fail(NHP_EHIP, "extract kernel returned status %u", status);
+  if (status == (uint32_t)(-NHP_EUNREACH))
+    return fail(NHP_EUNREACH, "no reached pose in the goal window (or back-tracking lost the path)");
+  if (best_ijt) memcpy(best_ijt, head + 2, 3 * sizeof(uint32_t));
+  if (goal_value_q10) *goal_value_q10 = head[5];
+  if (score_q10) *score_q10 = head[6];
+  if (n > NHP_MAX_STEPS_DEVICE || n > cap) return fail(NHP_ECAP, "plan has %u steps, buffer holds %u", n, cap);
+  std::vector<uint32_t> raw((size_t)n * nhp::kExStepWords);
+  if (n) {
+    HIP_CHECK(hipMemcpyAsync(raw.data(), plan->d.extract + nhp::kExHeader, raw.size() * 4, hipMemcpyDeviceToHost,
+                             plan->stream),
+              "extract copy");
+    HIP_CHECK(hipStreamSynchronize(plan->stream), "extract copy");
+  }
+  for (uint32_t k = 0; k < n; k++) {  // device order is goal -> start
+    const uint32_t* s = &raw[(size_t)(n - 1 - k) * nhp::kExStepWords];
+    nhp_step& o = h_steps[k];
+    memset(&o, 0, sizeof(o));
+    o.maneuver = (uint8_t)s[0];
+    o.steps = s[1];
+    o.from_ijt[0] = s[2];
+    o.from_ijt[1] = s[3];
+    o.from_ijt[2] = s[4];
+    o.to_ijt[0] = s[5];
+    o.to_ijt[1] = s[6];
+    o.to_ijt[2] = s[7];
+    o.cost_q10 = s[8];
+  }
+  return ok();
+}
+
+int plan_device_ptrs(const nhp_plan* plan, uint32_t** d_value, uint8_t** d_cspace) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (d_value) *d_value = plan->d.V;
+  if (d_cspace) *d_cspace = plan->d.B;
+  return ok();
+}
+
+int plan_get_tables(const nhp_plan* plan, int32_t* beta, int32_t* psi, int32_t* family, int32_t* fwd_sign,
+                    int32_t* skew, uint32_t* edge_len) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  const HostTables& t = plan->t;
+  if (beta) memcpy(beta, t.beta.data(), t.beta.size() * 4);
+  if (psi) memcpy(psi, t.psi.data(), t.psi.size() * 4);
+  if (family) memcpy(family, t.family.data(), t.family.size() * 4);
+  if (fwd_sign) memcpy(fwd_sign, t.fwd.data(), t.fwd.size() * 4);
+  if (skew) memcpy(skew, t.skew.data(), t.skew.size() * 4);
+  if (edge_len) memcpy(edge_len, t.edge_len.data(), t.edge_len.size() * 4);
+  return ok();
+}
+
+}  // extern "C"

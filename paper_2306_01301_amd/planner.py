@@ -1,0 +1,265 @@
+"""Python binding of libnhp.so (include/nhp.h).
+
+Argument marshalling only: every step of the planner runs in the HIP library.
+PyTorch provides the device memory (the plan's workspace is a torch tensor)
+and the stream (the current torch stream when the plan is made).  The binding
+raises if the library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnhp.so")
+
+INF = 0xFFFFFFFF
+HARD = 255
+LF, SF, RB, RF, SB, LB = range(6)
+NAMES = ("LF", "SF", "RB", "RF", "SB", "LB")
+DEFAULT_SCHEDULE = (LF, SF, RB, RF, SB, LB)
+MAX_STEPS_DEVICE = 4096
+
+STATUS = {0: "NHP_OK", -1: "NHP_EINVAL", -2: "NHP_ENOMEM", -3: "NHP_EHIP", -4: "NHP_ESTART",
+          -5: "NHP_EUNREACH", -6: "NHP_ECAP", -7: "NHP_ESTATE"}
+EINVAL, ENOMEM, EHIP, ESTART, EUNREACH, ECAP, ESTATE = -1, -2, -3, -4, -5, -6, -7
+
+
+class NhpParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_uint32),
+        ("ntheta", ctypes.c_uint32),
+        ("turn_radius", ctypes.c_double),
+        ("ct_q10", ctypes.c_uint32 * 6),
+        ("gear_q8", ctypes.c_uint32 * 6),
+        ("schedule", ctypes.c_uint8 * 6),
+        ("n_schedule", ctypes.c_uint8),
+        ("half_cell", ctypes.c_uint8),
+        ("reserved", ctypes.c_uint8 * 6),
+    ]
+
+
+class NhpStep(ctypes.Structure):
+    _fields_ = [
+        ("maneuver", ctypes.c_uint8),
+        ("pad", ctypes.c_uint8 * 3),
+        ("steps", ctypes.c_uint32),
+        ("from_ijt", ctypes.c_uint32 * 3),
+        ("to_ijt", ctypes.c_uint32 * 3),
+        ("cost_q10", ctypes.c_uint32),
+    ]
+
+
+# name -> (restype, argtypes); the full C ABI of include/nhp.h
+_vp, _u32, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32
+_PU32 = ctypes.POINTER(ctypes.c_uint32)
+SIGNATURES = {
+    "plan_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(NhpParams)]),
+    "plan_create": (ctypes.c_int, [ctypes.POINTER(NhpParams), _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "plan_destroy": (ctypes.c_int, [_vp]),
+    "plan_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "render_cspace": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32]),
+    "plan_set_cspace": (ctypes.c_int, [_vp, _vp]),
+    "sweep_n_turns": (ctypes.c_int, [_vp, _u32, _u32, _u32, _u32]),
+    "sweep_resume": (ctypes.c_int, [_vp, _u32]),
+    "sweep_one": (ctypes.c_int, [_vp, _u32]),
+    "extract_path": (ctypes.c_int, [_vp, _u32, _u32, _u32, _u32, _u32, _u32, ctypes.POINTER(NhpStep), _u32,
+                                    _PU32, _PU32, _PU32, _PU32]),
+    "plan_device_ptrs": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "plan_get_tables": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "plan_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libnhp.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libnhp.so is missing: build it with `python -m paper_2306_01301_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype, fn.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+class NhpError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        msg = lib().plan_last_error().decode(errors="replace")
+        super().__init__("%s: %s (%s)" % (what, STATUS.get(rc, rc), msg))
+        self.rc = rc
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise NhpError(rc, what)
+
+
+def make_params(nx: int, ntheta: int, turn_radius: float, ct_q10: Sequence[int],
+                gear_q8: Sequence[int] = (256,) * 6, schedule: Sequence[int] = DEFAULT_SCHEDULE,
+                half_cell: int = 1) -> NhpParams:
+    p = NhpParams()
+    p.nx, p.ntheta, p.turn_radius = int(nx), int(ntheta), float(turn_radius)
+    for k in range(6):
+        p.ct_q10[k] = int(ct_q10[k])
+        p.gear_q8[k] = int(gear_q8[k])
+        p.schedule[k] = int(schedule[k]) if k < len(schedule) else 0
+    p.n_schedule = len(schedule)
+    p.half_cell = int(half_cell)
+    return p
+
+
+def workspace_bytes(params: NhpParams) -> int:
+    return int(lib().plan_workspace_bytes(ctypes.byref(params)))
+
+
+@dataclass
+class Step:
+    maneuver: int
+    steps: int
+    frm: Tuple[int, int, int]
+    to: Tuple[int, int, int]
+    cost: int
+
+
+@dataclass
+class Path:
+    steps: List[Step]
+    best: Tuple[int, int, int]
+    value: int
+    score: int
+
+
+class Planner:
+    """One planning problem on one device: owns a workspace tensor and a plan."""
+
+    def __init__(self, nx: int, ntheta: int, turn_radius: float, ct_q10: Sequence[int],
+                 gear_q8: Sequence[int] = (256,) * 6, schedule: Sequence[int] = DEFAULT_SCHEDULE,
+                 half_cell: int = 1, device: Optional[torch.device] = None,
+                 stream: Optional[torch.cuda.Stream] = None, workspace: Optional[torch.Tensor] = None):
+        L = lib()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.params = make_params(nx, ntheta, turn_radius, ct_q10, gear_q8, schedule, half_cell)
+        self.nx, self.nt = int(nx), int(ntheta)
+        self.schedule = tuple(schedule)
+        nbytes = workspace_bytes(self.params)
+        if nbytes == 0:
+            raise NhpError(EINVAL, "plan_workspace_bytes")
+        if workspace is None:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-workspace.data_ptr()) % 256
+        self.ws = workspace[off:off + nbytes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._plan = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.plan_create(ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._plan)), "plan_create")
+        v, b = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(L.plan_device_ptrs(self._plan, ctypes.byref(v), ctypes.byref(b)), "plan_device_ptrs")
+        nr = self.nx * self.nx * self.nt
+        base = self.ws.data_ptr()
+        self._v_off, self._b_off = v.value - base, b.value - base
+        self.n_poses = nr
+
+    # ---- views of the plan's device volumes (no copies) ----
+    @property
+    def value(self) -> torch.Tensor:
+        """V as an int32 view [theta, y, x] (reinterpret as uint32 on the host)."""
+        nr = self.n_poses
+        return self.ws[self._v_off:self._v_off + 4 * nr].view(torch.int32).view(self.nt, self.nx, self.nx)
+
+    @property
+    def cspace(self) -> torch.Tensor:
+        nr = self.n_poses
+        return self.ws[self._b_off:self._b_off + nr].view(self.nt, self.nx, self.nx)
+
+    def value_numpy(self) -> np.ndarray:
+        self.stream.synchronize()
+        return self.value.cpu().numpy().view(np.uint32)
+
+    def cspace_numpy(self) -> np.ndarray:
+        self.stream.synchronize()
+        return self.cspace.cpu().numpy()
+
+    # ---- the pipeline ----
+    def render(self, image: torch.Tensor, vehicle: Sequence[int]) -> None:
+        assert image.dtype == torch.uint8 and image.is_cuda and image.shape == (self.nx, self.nx)
+        image = image.contiguous()
+        self._image = image  # keep alive until the render has run
+        f, r, s = (int(v) for v in vehicle)
+        _check(lib().render_cspace(self._plan, ctypes.c_void_p(image.data_ptr()), f, r, s), "render_cspace")
+
+    def set_cspace(self, cspace: torch.Tensor) -> None:
+        assert cspace.dtype == torch.uint8 and cspace.is_cuda and cspace.numel() == self.n_poses
+        cspace = cspace.contiguous()
+        self._cs = cspace
+        _check(lib().plan_set_cspace(self._plan, ctypes.c_void_p(cspace.data_ptr())), "plan_set_cspace")
+
+    def sweep(self, start: Sequence[int], n_cycles: int) -> None:
+        i, j, t = (int(v) for v in start)
+        _check(lib().sweep_n_turns(self._plan, i, j, t, int(n_cycles)), "sweep_n_turns")
+
+    def resume(self, n_cycles: int) -> None:
+        _check(lib().sweep_resume(self._plan, int(n_cycles)), "sweep_resume")
+
+    def sweep_one(self, maneuver: int) -> None:
+        _check(lib().sweep_one(self._plan, int(maneuver)), "sweep_one")
+
+    def extract(self, goal: Sequence[int], radius: int = 0, w_xy: int = 1024, w_t: int = 1024,
+                cap: int = MAX_STEPS_DEVICE) -> Path:
+        steps = (NhpStep * max(1, cap))()
+        n, best, val, score = ctypes.c_uint32(), (ctypes.c_uint32 * 3)(), ctypes.c_uint32(), ctypes.c_uint32()
+        gi, gj, gt = (int(v) for v in goal)
+        rc = lib().extract_path(self._plan, gi, gj, gt, int(radius), int(w_xy), int(w_t), steps, int(cap),
+                                ctypes.byref(n), best, ctypes.byref(val), ctypes.byref(score))
+        _check(rc, "extract_path")
+        out = [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_ijt),
+                    tuple(int(v) for v in s.to_ijt), int(s.cost_q10)) for s in steps[: n.value]]
+        return Path(out, tuple(int(v) for v in best), int(val.value), int(score.value))
+
+    def tables(self) -> dict:
+        L, N = self.nt, self.nx
+        out = dict(beta=np.zeros(L, np.int32), psi=np.zeros(L, np.int32), I=np.zeros(L, np.int32),
+                   J=np.zeros(L, np.int32), Bsk=np.zeros((L, N), np.int32), Lq=np.zeros((6, L), np.uint32))
+        _check(lib().plan_get_tables(self._plan, *[ctypes.c_void_p(out[k].ctypes.data) for k in
+                                                   ("beta", "psi", "I", "J", "Bsk", "Lq")]), "plan_get_tables")
+        return out
+
+    def set_stream(self, stream: torch.cuda.Stream) -> None:
+        self.stream = stream
+        _check(lib().plan_set_stream(self._plan, ctypes.c_void_p(stream.cuda_stream)), "plan_set_stream")
+
+    def close(self) -> None:
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            lib().plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def planner_for(scene, **kw) -> Planner:
+    """A Planner with a scene's parameters (see scenes.Scene)."""
+    return Planner(scene.nx, scene.nt, scene.R, scene.ct, scene.gear, scene.schedule, scene.half_cell, **kw)
+
+
+def plan_scene(scene, radius: Optional[int] = None, device=None) -> Tuple[Planner, Path]:
+    """Render, sweep and extract one scene on the GPU."""
+    p = planner_for(scene, device=device)
+    img = torch.from_numpy(np.ascontiguousarray(scene.image)).to(p.device)
+    p.render(img, scene.vehicle)
+    p.sweep(scene.start, scene.n_cycles)
+    path = p.extract(scene.goal, scene.goal_radius if radius is None else radius, scene.w_xy, scene.w_t)
+    return p, path
