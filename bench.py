@@ -1,0 +1,232 @@
+"""Benchmark of the kernel-style N-turn planner hot path on one MI355X.
+
+One step = one whole plan of the 512 x 512 x 512 maze with N = 20 maneuver
+cycles, inputs resident in HBM: obstacle rendering, init, 120 maneuver
+sweeps, goal search and back-tracking (the planner object and its tables are
+made once, before timing, like the paper's `ini`).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  `value` is pose-cell updates per second over whole
+steps (6 N N_R updates per plan); plans/s, sweep-only throughput, per-stage
+times and p50/p99 plan latency ride along.  `roofline` covers the dominant
+kernel (the turn sweep) from HIP events recorded on the plan's stream during
+the timed steps; `cpu_baseline` times the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pose-cell updates/s and plans/s at 512³ N=20; p50/p99 plan latency batched vs single"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 9  # read V (4 B) + read obstacle code (1 B) + write V (4 B)
+TURNS = (0, 2, 3, 5)   # LF, RB, RF, LB
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_turn_sweep_maze_512.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("k_sweep.hip", "nhp_internal.h"):
+        with open(os.path.join(ROOT, "paper_2306_01301_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per turn-sweep launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_model() -> str:
+    try:
+        out = subprocess.check_output(["lscpu"], text=True)
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(scene, cycles: int):
+    """The oracle as it stands, on the host's cores, on `cycles` maneuver
+    cycles of the same workload (a bounded sample of the 20)."""
+    import oracle
+
+    oracle.build()
+    threads = oracle.set_threads(os.cpu_count() or 1)
+    prob = oracle.Problem(scene.nx, scene.nt, scene.R, scene.half_cell, list(scene.schedule), list(scene.ct),
+                          list(scene.gear))
+    B = oracle.render(prob, scene.image, *scene.vehicle)
+    V = oracle.init(prob, B, scene.start)
+    t0 = time.perf_counter()
+    oracle.cycles(prob, B, V, cycles)
+    dt = time.perf_counter() - t0
+    updates = len(scene.schedule) * cycles * scene.n_poses
+    return {"value": updates / dt, "unit": "pose-cell updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d maneuver cycles (%d sweeps, %.2e pose updates) of %s on %d threads of %s, %.1f s"
+                      % (cycles, scene.n_cycles, len(scene.schedule) * cycles, updates, scene.name, threads,
+                         cpu_model(), dt)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="maze_512")
+    ap.add_argument("--cpu-cycles", type=int, default=2, help="oracle cycles timed for cpu_baseline (0: skip)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain device copy of 1 GiB (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2306_01301_amd import planner, scenes, sizing
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    sc = scenes.WORKLOADS[args.workload]()
+    if args.calibrate_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    p = planner.planner_for(sc)
+    image = torch.from_numpy(np.ascontiguousarray(sc.image)).cuda()
+    stream = p.stream
+    n_sched = len(sc.schedule)
+
+    def one_plan(events):
+        """One step.  events: list to append (tag, event) pairs to, or None."""
+        def mark(tag):
+            if events is not None:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record(stream)
+                events.append((tag, e))
+        mark("start")
+        p.render(image, sc.vehicle)
+        mark("render")
+        p.sweep(sc.start, 0)  # init: V = INF, V(start) = 0
+        mark("init")
+        for _ in range(sc.n_cycles):
+            for mu in sc.schedule:
+                p.sweep_one(mu)
+                mark(mu)
+        path = p.extract(sc.goal, sc.goal_radius, sc.w_xy, sc.w_t)
+        mark("extract")
+        return path
+
+    for _ in range(args.warmup):
+        one_plan(None)
+    torch.cuda.synchronize()
+
+    step_events = []
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ev = []
+        ts = time.perf_counter()
+        path = one_plan(ev)
+        lat.append(time.perf_counter() - ts)  # extract synchronises: submission to plan on the host
+        step_events.append(ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    # per-stage and per-kernel durations from the events (plan's stream)
+    stage = {"render": [], "init": [], "sweeps": [], "extract": []}
+    turn_ms, straight_ms = [], []
+    for ev in step_events:
+        t = {}
+        prev = None
+        sweeps = 0.0
+        for tag, e in ev:
+            if prev is not None:
+                dt = prev[1].elapsed_time(e)
+                if tag in ("render", "init", "extract"):
+                    t[tag] = dt
+                else:
+                    sweeps += dt
+                    (turn_ms if tag in TURNS else straight_ms).append(dt)
+            prev = (tag, e)
+        for k in ("render", "init", "extract"):
+            stage[k].append(t[k])
+        stage["sweeps"].append(sweeps)
+
+    updates = sizing.pose_updates(sc.nx, sc.nt, sc.n_cycles, n_sched)
+    ms_per_step = 1000.0 * wall / args.steps
+    turn_avg_ms = float(np.mean(turn_ms))
+    alg_bytes = BYTES_PER_UPDATE * sc.n_poses
+    achieved = alg_bytes / (turn_avg_ms * 1e-3) / 1e9
+    sweep_ms = float(np.median(stage["sweeps"]))
+    lat_ms = np.array(lat) * 1000.0
+    out = {
+        "metric": METRIC,
+        "value": updates / (ms_per_step * 1e-3),
+        "unit": "pose-cell updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": sc.name, "grid": [sc.nx, sc.nx, sc.nt], "n_cycles": sc.n_cycles,
+                   "sweeps_per_plan": n_sched * sc.n_cycles, "pose_updates_per_plan": updates,
+                   "vehicle_box_frs": list(sc.vehicle), "turn_radius_cells": sc.R, "plans_per_step": 1},
+        "plans_per_s": 1000.0 / ms_per_step,
+        "sweep_updates_per_s": updates / (sweep_ms * 1e-3),
+        "latency_ms": {"single": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+                       "batched": None},
+        "stages_ms": {k: float(np.median(v)) for k, v in stage.items()},
+        "plan": {"maneuvers": len(path.steps), "cost_cells": path.value / 1024.0, "best": list(path.best)},
+        "roofline": {"kernel": "row_sweep_kernel<32, cyclic> (turn sweep, 4 of 6 sweeps)", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(), "bytes_per_launch_algorithmic": alg_bytes,
+                     "avg_launch_ms": turn_avg_ms, "launches_timed": len(turn_ms),
+                     "straight_avg_launch_ms": float(np.mean(straight_ms))},
+    }
+    p.close()
+    if args.cpu_cycles > 0:
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_cycles)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
