@@ -214,13 +214,15 @@ def parking_256(seed: int = 1303) -> Scene:
 def maze_512(seed: int = 1304) -> Scene:
     """512 x 512 cells x 512 headings maze (16 x 16 maze cells, 28-cell
     corridors, 4-cell walls), vehicle 10 x 5, R = 12, soft ramp within 4 cells
-    of walls, N = 20, start and goal at opposite corners."""
+    of walls, N = 20, start and goal at the centres of opposite corner cells.
+    The start faces +x, the goal -x (180 degrees), a heading at which 20
+    cycles reach the far corner of this maze."""
     rng = np.random.default_rng(seed)
     n_cells, pitch, wall = 16, 32, 4
     img = soft_ramp(maze(rng, n_cells, pitch, wall), 4.0, 64)
     c0 = wall + (pitch - wall) // 2
     c1 = (n_cells - 1) * pitch + c0
-    return Scene("maze_512", 512, 512, 12.0, img, vehicle_box(10, 5), (c0, c0, 0), (c1, c1, 0),
+    return Scene("maze_512", 512, 512, 12.0, img, vehicle_box(10, 5), (c0, c0, 0), (c1, c1, 256),
                  n_cycles=20, ct=uniform_ct(24), half_cell=1, goal_radius=2, seed=seed)
 
 
