@@ -20,6 +20,35 @@ __device__ __forceinline__ int wrapn(int v, int N) { return v - ((v >= N) ? N : 
 __device__ __forceinline__ int tap_dx(int32_t p) { return (int)(p & 0xffff); }
 __device__ __forceinline__ int tap_dy(int32_t p) { return (int)((uint32_t)p >> 16); }
 
+// Samples of a pass are read 4 at a time with independent loads (the tap
+// count is a run-time value, so a plain loop would serialise them).
+template <bool WALLED>
+__device__ __forceinline__ uint32_t max_over(const uint8_t* __restrict__ src, const int32_t* __restrict__ tp, int n,
+                                             int i, int j, int N) {
+  uint32_t m = 0;
+  int g = 0;
+  for (; g + 4 <= n; g += 4) {
+    uint32_t q[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int32_t t = tp[g + e];
+      const int y = wrapn(j + tap_dy(t), N), x = wrapn(i + tap_dx(t), N);
+      q[e] = src[(size_t)y * N + x];
+      if (WALLED) q[e] = (y == 0 || x == 0) ? kHard : q[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) m = q[e] > m ? q[e] : m;
+  }
+  for (; g < n; g++) {
+    const int32_t t = tp[g];
+    const int y = wrapn(j + tap_dy(t), N), x = wrapn(i + tap_dx(t), N);
+    uint32_t q = src[(size_t)y * N + x];
+    if (WALLED) q = (y == 0 || x == 0) ? kHard : q;
+    m = q > m ? q : m;
+  }
+  return m;
+}
+
 // side[T][j][i] = max over sideways samples of the walled image
 __global__ __launch_bounds__(256) void render_side_kernel(const uint8_t* __restrict__ image, uint8_t* __restrict__ side,
                                                           const int32_t* __restrict__ taps, int N, int n_side) {
@@ -27,14 +56,7 @@ __global__ __launch_bounds__(256) void render_side_kernel(const uint8_t* __restr
   const int j = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const int32_t* tp = taps + (size_t)T * 2 * kMaxTaps;
-  uint32_t m = 0;
-  for (int g = 0; g < n_side; g++) {
-    const int32_t t = tp[g];
-    const int y = wrapn(j + tap_dy(t), N), x = wrapn(i + tap_dx(t), N);
-    const uint32_t q = (y == 0 || x == 0) ? kHard : (uint32_t)image[(size_t)y * N + x];
-    m = q > m ? q : m;
-  }
+  const uint32_t m = max_over<true>(image, taps + (size_t)T * 2 * kMaxTaps, n_side, i, j, N);
   side[((size_t)T * N + j) * N + i] = (uint8_t)m;
 }
 
@@ -46,15 +68,7 @@ __global__ __launch_bounds__(256) void render_len_kernel(const uint8_t* __restri
   const int j = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const int32_t* tp = taps + (size_t)T * 2 * kMaxTaps + kMaxTaps;
-  const uint8_t* sp = side + (size_t)T * N * N;
-  uint32_t m = 0;
-  for (int g = 0; g < n_len; g++) {
-    const int32_t t = tp[g];
-    const int y = wrapn(j + tap_dy(t), N), x = wrapn(i + tap_dx(t), N);
-    const uint32_t q = sp[(size_t)y * N + x];
-    m = q > m ? q : m;
-  }
+  uint32_t m = max_over<false>(side + (size_t)T * N * N, taps + (size_t)T * 2 * kMaxTaps + kMaxTaps, n_len, i, j, N);
   if (i == 0 || j == 0) m = kHard;
   B[((size_t)T * N + j) * N + i] = (uint8_t)m;
 }

@@ -66,6 +66,11 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
+// Workgroup barrier that waits only for this wave's LDS operations, not for
+// its outstanding global loads (__syncthreads waits for both), so loads
+// issued for the next chunk stay in flight across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 struct SweepArgs {
   uint32_t* V;
   const uint8_t* B;
@@ -106,6 +111,7 @@ __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepArgs a, const int3
                                                         const int32_t* __restrict__ fwd, int mu_forward) {
   __shared__ uint32_t aggD[16][64];
   __shared__ uint32_t aggC[16][64];
+  __shared__ uint32_t wlut[256];  // edge weight by obstacle code (INF for hard)
   const int S = blockDim.x >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -129,6 +135,7 @@ __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepArgs a, const int3
     dir = (fwd[T0] > 0) == (mu_forward != 0);
     sk = skew + (size_t)T0 * N;
   }
+  for (int c = threadIdx.x; c < 256; c += blockDim.x) wlut[c] = weight((uint32_t)c, base, l4);
 
   uint32_t u[P];
   uint32_t code[P];
@@ -172,14 +179,17 @@ __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepArgs a, const int3
     code[k] = a.B[cell];
   }
 
-  // compose the section into (D, C)
+  __syncthreads();  // weight table ready
+  // weights replace the codes in place; compose the section into (D, C):
+  // min(C + w, u + ct + w) = min(C, u + ct) + w (saturating add is monotone)
   uint32_t D = 0, C = kInf;
+#pragma unroll
+  for (int k = 0; k < P; k++) code[k] = wlut[code[k]];
 #pragma unroll
   for (int k = 0; k < P; k++) {
     if (k < n_real) {
-      const uint32_t w = weight(code[k], base, l4);
-      C = umin(sadd(C, w), sadd(sadd(u[k], a.ct), w));
-      D = sadd(D, w);
+      C = sadd(umin(C, sadd(u[k], a.ct)), code[k]);
+      D = sadd(D, code[k]);
     }
   }
   aggD[wave][lane] = D;
@@ -187,13 +197,13 @@ __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepArgs a, const int3
   __syncthreads();
   uint32_t v = section_carry<CYCLIC>(aggD, aggC, S, wave, lane);
 
-  // replay and store
+  // replay: a hard pose has weight INF, and w >> 31 (arithmetic) is then all
+  // ones, which forces its output to INF
 #pragma unroll
   for (int k = 0; k < P; k++) {
-    const uint32_t cv = code[k];
-    const uint32_t w = weight(cv, base, l4);
+    const uint32_t w = code[k];
     const uint32_t uu = u[k];
-    u[k] = (cv == kHard) ? kInf : umin(v, uu);
+    u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
     v = sadd(umin(v, sadd(uu, a.ct)), w);
   }
   // recompute the column of every step rather than keeping P of them live
@@ -239,6 +249,7 @@ __global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const in
   __shared__ int32_t tS[Q];
   __shared__ uint32_t aggD[4][64];
   __shared__ uint32_t aggC[4][64];
+  __shared__ uint32_t wlut[256];
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -249,7 +260,7 @@ __global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const in
   const int T = planes[tile / tiles_x];
   const uint32_t plane = (uint32_t)T * (uint32_t)N * (uint32_t)N;
   const uint32_t Lq = edge_len[T];
-  const uint32_t base = 256u * Lq + 128u, l4 = 4u * Lq;
+  wlut[tid] = weight((uint32_t)tid, 256u * Lq + 128u, 4u * Lq);
   const int dir = (fwd[T] > 0) == (mu_forward != 0);
   const int16_t* sk = skew + (size_t)T * N;
   const int kk = tid % Q;       // column of this thread in the load/store phases
@@ -297,7 +308,7 @@ __global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const in
     __syncthreads();
 
     // scan: wave w takes columns [w SUB, (w+1) SUB) of the chunk for all 64 lines
-    uint32_t u[SUB], cb[SUB];
+    uint32_t u[SUB], w[SUB];
     int rr[SUB];
 #pragma unroll
     for (int q = 0; q < SUB; q++) {
@@ -305,16 +316,14 @@ __global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const in
       const bool ok = kq < nq;
       rr[q] = ok ? lane + tS[kq] - bmin : 0;  // in [0, rows) for real columns
       u[q] = ok ? tV[rr[q] * PITCH + kq] : kInf;
-      cb[q] = ok ? tB[rr[q] * PITCH + kq] : 0u;
+      w[q] = ok ? wlut[tB[rr[q] * PITCH + kq]] : 0u;
     }
     uint32_t D = 0, C = kInf;
 #pragma unroll
     for (int q = 0; q < SUB; q++) {
       const bool ok = wave * SUB + q < nq;
-      const uint32_t w = ok ? weight(cb[q], base, l4) : 0u;
-      const uint32_t cq = ok ? sadd(sadd(u[q], a.ct), w) : kInf;
-      C = umin(sadd(C, w), cq);
-      D = sadd(D, w);
+      C = ok ? sadd(umin(C, sadd(u[q], a.ct)), w[q]) : C;
+      D = sadd(D, w[q]);
     }
     aggD[wave][lane] = D;
     aggC[wave][lane] = C;
@@ -325,9 +334,8 @@ __global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const in
     for (int q = 0; q < SUB; q++) {
       const int kq = wave * SUB + q;
       if (kq < nq && line_ok) {
-        const uint32_t w = weight(cb[q], base, l4);
-        tV[rr[q] * PITCH + kq] = (cb[q] == kHard) ? kInf : umin(v, u[q]);
-        v = sadd(umin(v, sadd(u[q], a.ct)), w);
+        tV[rr[q] * PITCH + kq] = umin(v, u[q]) | (uint32_t)((int32_t)w[q] >> 31);
+        v = sadd(umin(v, sadd(u[q], a.ct)), w[q]);
       }
     }
     for (int s = 0; s < 4; s++) carry = umin(sadd(carry, aggD[s][lane]), aggC[s][lane]);
@@ -372,6 +380,8 @@ __global__ void walls_kernel(uint8_t* __restrict__ B, int N, int L) {
 
 // Steps per wave: the smallest power of two in [8, 64] that splits the curve
 // into at most 16 sections (16 waves of a 1024-thread workgroup).
+constexpr int XQ = 32;  // columns per x-major chunk
+
 int pick_section(int len) {
   int P = 8;
   while (P < 64 && P * 16 < len) P <<= 1;
@@ -438,7 +448,7 @@ hipError_t launch_sweep(const DevPlan& d, int mu, hipStream_t s) {
       if (e != hipSuccess) return e;
     }
     if (d.n_planes_x > 0) {
-      hipLaunchKernelGGL((xmajor_sweep_kernel<32>), dim3(tiles_x * d.n_planes_x), dim3(256), 0, s, a, d.skew,
+      hipLaunchKernelGGL((xmajor_sweep_kernel<XQ>), dim3(tiles_x * d.n_planes_x), dim3(256), 0, s, a, d.skew,
                          d.planes, el, d.fwd, mu_fwd);
       e = hipGetLastError();
     }
