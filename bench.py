@@ -89,15 +89,73 @@ def cpu_baseline(scene, cycles: int):
                          cpu_model(), dt)}
 
 
+def batch_comparison() -> dict:
+    """64 mixed planning instances submitted at once: one plan per launch vs
+    shared launches.  Latency of a plan = completion - submission."""
+    from paper_2306_01301_amd import scenes, serving, sizing
+
+    reqs = scenes.batch_64()
+    updates = sum(sizing.pose_updates(s.nx, s.nt, s.n_cycles, len(s.schedule)) for s in reqs)
+    serving.run_batched(reqs[:8])  # warm-up
+    serving.run_single(reqs[:8])
+    out = {"workload": "batch_64", "plans": len(reqs), "pose_updates": updates}
+    for name, fn in (("one_plan_per_launch", serving.run_single), ("batched", serving.run_batched)):
+        res = fn(reqs)
+        s = serving.latency_summary(res)
+        s["pose_updates_per_s"] = updates / max(r.finished for r in res)
+        out[name] = s
+    return out
+
+
+def bench_serving(args) -> int:
+    """Continuous batching under Poisson arrivals of mixed requests (sides up
+    to 1024, headings up to 512, N up to 20), admitted by HBM footprint."""
+    import torch
+
+    from paper_2306_01301_amd import scenes, serving, sizing
+
+    reqs = scenes.serving_requests(count=args.requests)
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    rates = [float(r) for r in args.rates.split(",") if r]
+    warm = serving.Server(budget, max_live=64)
+    warm.run(reqs[:4], [0.0] * 4)
+    warm.close()
+    per_rate = []
+    for rate in rates:
+        arr = scenes.poisson_arrivals(1306 + int(rate), rate, len(reqs))
+        srv = serving.Server(budget, max_live=64)
+        res = srv.run(reqs, arr)
+        srv.close()
+        s = serving.latency_summary(res)
+        s["rate"] = rate
+        per_rate.append(s)
+        print(json.dumps({"rate": rate, **{k: v for k, v in s.items() if k != "rate"}}), file=sys.stderr, flush=True)
+    updates = sum(sizing.pose_updates(s.nx, s.nt, s.n_cycles, len(s.schedule)) for s in reqs)
+    best = max(per_rate, key=lambda s: s["plans_per_s"] or 0)
+    out = {"metric": METRIC, "value": best["plans_per_s"], "unit": "plans/s", "n_gpus": 1, "steps": len(rates),
+           "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "serving_requests", "requests": len(reqs), "pose_updates": updates,
+                      "hbm_budget_bytes": budget, "admission": "25 B/pose (3 vertices x 2 gears x 4 B + 1 B)"},
+           "serving": per_rate}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="maze_512")
-    ap.add_argument("--cpu-cycles", type=int, default=2, help="oracle cycles timed for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-cycles", type=int, default=20, help="oracle cycles timed for cpu_baseline (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of 1 GiB (counter calibration)")
+    ap.add_argument("--skip-batch", action="store_true", help="skip the batched-vs-single comparison")
+    ap.add_argument("--rates", default="10,20,50,100,200,500",
+                    help="serving workload: Poisson arrival rates in plans/s")
+    ap.add_argument("--requests", type=int, default=48, help="serving workload: requests per rate")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -114,6 +172,8 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
+    if args.workload == "serving":
+        return bench_serving(args)
     sc = scenes.WORKLOADS[args.workload]()
     if args.calibrate_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -220,6 +280,8 @@ def main() -> int:
                      "straight_avg_launch_ms": float(np.mean(straight_ms))},
     }
     p.close()
+    if not args.skip_batch:
+        out["latency_ms"]["batch_64"] = batch_comparison()
     if args.cpu_cycles > 0:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_cycles)
     else:

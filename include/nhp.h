@@ -169,6 +169,59 @@ int plan_device_ptrs(const nhp_plan* plan, uint32_t** d_value, uint8_t** d_cspac
 int plan_get_tables(const nhp_plan* plan, int32_t* beta, int32_t* psi, int32_t* family,
                     int32_t* fwd_sign, int32_t* skew, uint32_t* edge_len);
 
+/* ------------------------------------------------------------------------
+ * Batched execution.  A batch drives many plans with shared launches: one
+ * launch per pass covers the current work of every listed plan (tiles of all
+ * plans in one grid), so small plans fill the GPU together and a plan that
+ * joins later runs alongside plans that are further along (continuous
+ * batching).  Work is enqueued on the batch's stream; work the plans have on
+ * other streams must be complete.  A plan may appear once per call.  Job
+ * tables live in a ring of 4 pinned/device buffer pairs owned by the batch;
+ * a call waits only when it reuses a buffer whose launches are still queued.
+ * Every entry point returns a status; plan_last_error() explains failures.
+ * ------------------------------------------------------------------------ */
+typedef struct nhp_batch nhp_batch;
+
+/* A batch for up to `capacity` plans per call, enqueueing on `stream`. */
+int batch_create(uint32_t capacity, void* stream, nhp_batch** out);
+
+/* Waits for the batch's stream and frees its buffers (NULL accepted). */
+int batch_destroy(nhp_batch* batch);
+
+/* Obstacle rendering (as render_cspace) of n plans in two launches.
+ * d_images[k]: plan k's image (device); boxes_frs[3k..3k+2]: its box. */
+int batch_render(nhp_batch* batch, nhp_plan* const* plans, const uint8_t* const* d_images,
+                 const int32_t* boxes_frs, uint32_t n);
+
+/* V = NHP_INF and V(start) = 0 for n plans in one launch (starts_ijt[3k..]).
+ * Errors: NHP_ESTATE, NHP_EINVAL, NHP_ESTART (checked on the host). */
+int batch_init(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* starts_ijt, uint32_t n);
+
+/* One tick of continuous batching: plan k runs its sweep number steps[k],
+ * i.e. maneuver schedule[steps[k] % n_schedule] (Insert 1), all plans in
+ * at most five launches (turn and y-major straight tiles grouped by section
+ * size, x-major straight tiles).  Errors: NHP_ESTATE (no batch_init or
+ * sweep_n_turns yet), NHP_EINVAL. */
+int batch_step(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* steps, uint32_t n);
+
+/* batch_init, then step s = 0, 1, ... covering every plan k with
+ * s < n_cycles[k] * n_schedule: plan k ends with n_cycles[k] cycles, as
+ * sweep_n_turns would leave it. */
+int batch_sweep(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* starts_ijt,
+                const uint32_t* n_cycles, uint32_t n);
+
+/* Goal search and back-tracking (as extract_path) for n plans in one launch,
+ * one workgroup per plan.  Per plan k: goal goals_ijt[3k..], radius[k],
+ * weights w_xy_q10[k], w_t_q10[k]; results status[k] (NHP_OK, NHP_EUNREACH
+ * or NHP_ECAP), n_steps[k], steps in h_steps[k * cap_per_plan ...] start ->
+ * goal, and (optional arrays) best_ijt[3k..], goal_value_q10[k],
+ * score_q10[k].  Synchronises the batch's stream.  The call returns NHP_OK
+ * when it ran, whatever the per-plan statuses. */
+int batch_extract(nhp_batch* batch, nhp_plan* const* plans, uint32_t n, const uint32_t* goals_ijt,
+                  const uint32_t* radius, const uint32_t* w_xy_q10, const uint32_t* w_t_q10,
+                  nhp_step* h_steps, uint32_t cap_per_plan, uint32_t* n_steps, int32_t* status,
+                  uint32_t* best_ijt, uint32_t* goal_value_q10, uint32_t* score_q10);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* plan_last_error(void);
 

@@ -19,9 +19,20 @@ constexpr int kWaves = kThreads / 64;
 
 __device__ __forceinline__ uint32_t sadd(uint32_t a, uint32_t b) { return __builtin_elementwise_add_sat(a, b); }
 
-__device__ __forceinline__ int wrapn(long v, int n) {
-  long r = v % n;
-  return (int)(r < 0 ? r + n : r);
+// v mod n for any v (goal window coordinates, once per candidate)
+__device__ __forceinline__ int modn(int v, int n) {
+  const int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// v mod n for v in [-2n, 3n): the back-tracking callers add or subtract at
+// most two values below n (table offsets are reduced, skews are below n, k < L)
+__device__ __forceinline__ int wrapn(int v, int n) {
+  v += (v < 0) ? n : 0;
+  v += (v < 0) ? n : 0;
+  v -= (v >= n) ? n : 0;
+  v -= (v >= n) ? n : 0;
+  return v;
 }
 
 __device__ __forceinline__ uint32_t weight(uint32_t code, uint32_t Lq) {
@@ -29,29 +40,43 @@ __device__ __forceinline__ uint32_t weight(uint32_t code, uint32_t Lq) {
   return (uint32_t)(((uint64_t)Lq * (256u + 4u * code) + 128u) >> 8);
 }
 
-// inclusive saturating prefix sum over the block, k-th thread gets sum of 0..k
-__device__ uint32_t block_scan_sat(uint32_t x, uint32_t* red) {
+// Inclusive saturating prefix sums over the block of M values per thread at
+// once (one per scheduled maneuver): thread k gets, for each m, the sum of
+// x[m] over threads 0..k.
+template <int M>
+__device__ void block_scan_sat(uint32_t (&x)[M], uint32_t (*red)[kWaves]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x = sadd(x, y);
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+      const uint32_t y = __shfl_up(x[m], o, 64);
+      if (lane >= o) x[m] = sadd(x[m], y);
+    }
   }
-  if (lane == 63) red[wave] = x;
+  if (lane == 63) {
+#pragma unroll
+    for (int m = 0; m < M; m++) red[m][wave] = x[m];
+  }
   __syncthreads();
   if (wave == 0) {
-    uint32_t t = lane < kWaves ? red[lane] : 0u;
 #pragma unroll
-    for (int o = 1; o < kWaves; o <<= 1) {
-      const uint32_t y = __shfl_up(t, o, 64);
-      if (lane >= o) t = sadd(t, y);
+    for (int m = 0; m < M; m++) {
+      uint32_t t = lane < kWaves ? red[m][lane] : 0u;
+#pragma unroll
+      for (int o = 1; o < kWaves; o <<= 1) {
+        const uint32_t y = __shfl_up(t, o, 64);
+        if (lane >= o) t = sadd(t, y);
+      }
+      if (lane < kWaves) red[m][lane] = t;
     }
-    if (lane < kWaves) red[lane] = t;
   }
   __syncthreads();
-  if (wave > 0) x = sadd(x, red[wave - 1]);
+  if (wave > 0) {
+#pragma unroll
+    for (int m = 0; m < M; m++) x[m] = sadd(x[m], red[m][wave - 1]);
+  }
   __syncthreads();
-  return x;
 }
 
 __device__ uint64_t block_min_u64(uint64_t x, uint64_t* red) {
@@ -69,12 +94,6 @@ __device__ uint64_t block_min_u64(uint64_t x, uint64_t* red) {
   return r;
 }
 
-struct ExArgs {
-  DevPlan d;
-  uint32_t si, sj, st, gi, gj, gt;
-  int radius;
-  uint32_t w_xy, w_t;
-};
 
 __device__ __forceinline__ size_t pose_index(int N, int i, int j, int T) {
   return ((size_t)T * N + j) * N + i;
@@ -90,10 +109,10 @@ __device__ bool predecessor(const DevPlan& d, int mu, int i, int j, int T, int k
     const bool asc = (mu == NHP_LF || mu == NHP_RB);
     const int32_t* ox = d.turn_off + (left ? 0 : 2) * L;
     const int32_t* oy = d.turn_off + (left ? 1 : 3) * L;
-    const int xp = wrapn((long)i - ox[T], N), yp = wrapn((long)j - oy[T], N);
-    const int Tk = wrapn(asc ? (long)T - k : (long)T + k, L);
-    *pi = wrapn((long)xp + ox[Tk], N);
-    *pj = wrapn((long)yp + oy[Tk], N);
+    const int xp = wrapn((int)i - ox[T], N), yp = wrapn((int)j - oy[T], N);
+    const int Tk = wrapn(asc ? (int)T - k : (int)T + k, L);
+    *pi = wrapn((int)xp + ox[Tk], N);
+    *pj = wrapn((int)yp + oy[Tk], N);
     *pT = Tk;
     return true;
   }
@@ -102,20 +121,18 @@ __device__ bool predecessor(const DevPlan& d, int mu, int i, int j, int T, int k
   const int16_t* sk = d.skew + (size_t)T * N;
   const int c = fam_x ? i : j;
   const int other = fam_x ? j : i;
-  const int xp = wrapn((long)other - sk[c], N);
+  const int xp = wrapn((int)other - sk[c], N);
   const int step = asc ? c : N - 1 - c;  // the kernels walk N-1 .. 0 when descending
   if (k > step) return false;
   const int c2 = asc ? step - k : N - 1 - (step - k);
-  const int o2 = wrapn((long)xp + sk[c2], N);
+  const int o2 = wrapn((int)xp + sk[c2], N);
   *pi = fam_x ? c2 : o2;
   *pj = fam_x ? o2 : c2;
   *pT = T;
   return true;
 }
 
-__global__ __launch_bounds__(kThreads) void extract_kernel(ExArgs x) {
-  __shared__ uint32_t red32[kWaves];
-  __shared__ uint64_t red64[kWaves];
+__device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[kWaves], uint64_t* red64) {
   const DevPlan& d = x.d;
   const int N = d.nx, L = d.nt;
   const int tid = threadIdx.x;
@@ -126,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void extract_kernel(ExArgs x) {
   uint64_t key = ~0ull;
   for (int c = tid; c < nc; c += kThreads) {
     const int dx = c % W - r, dy = (c / W) % W - r, dt = c / (W * W) - r;
-    const int i = wrapn((long)x.gi + dx, N), j = wrapn((long)x.gj + dy, N), T = wrapn((long)x.gt + dt, L);
+    const int i = modn((int)x.gi + dx, N), j = modn((int)x.gj + dy, N), T = modn((int)x.gt + dt, L);
     const size_t q = pose_index(N, i, j, T);
     const uint32_t v = d.V[q];
     if (d.B[q] == kHard || v == kInf) continue;
@@ -145,9 +162,9 @@ __global__ __launch_bounds__(kThreads) void extract_kernel(ExArgs x) {
     }
     return;
   }
-  int ci = wrapn((long)x.gi + (int)(key & 63) - r, N);
-  int cj = wrapn((long)x.gj + (int)((key >> 6) & 63) - r, N);
-  int cT = wrapn((long)x.gt + (int)((key >> 12) & 63) - r, L);
+  int ci = modn((int)x.gi + (int)(key & 63) - r, N);
+  int cj = modn((int)x.gj + (int)((key >> 6) & 63) - r, N);
+  int cT = modn((int)x.gt + (int)((key >> 12) & 63) - r, L);
   if (tid == 0) {
     out[2] = ci;
     out[3] = cj;
@@ -168,22 +185,35 @@ __global__ __launch_bounds__(kThreads) void extract_kernel(ExArgs x) {
       status = (uint32_t)(-NHP_EUNREACH);
       break;
     }
-    uint64_t best = ~0ull;
-    for (int pos = 0; pos < d.n_schedule; pos++) {
-      const int mu = d.schedule[pos];
-      int pi = 0, pj = 0, pT = 0;
-      const bool ok = predecessor(d, mu, ci, cj, cT, k, &pi, &pj, &pT);
-      uint32_t w = kInf, vq = kInf;
-      if (ok) {
-        const size_t q = pose_index(N, pi, pj, pT);
-        w = weight(d.B[q], d.edge_len[(size_t)mu * L + pT]);
-        vq = d.V[q];
+    // candidates k = tid + 1 of every scheduled maneuver: all loads first
+    uint32_t w[6], vq[6];
+    bool ok[6];
+#pragma unroll
+    for (int pos = 0; pos < 6; pos++) {
+      w[pos] = kInf;
+      vq[pos] = kInf;
+      ok[pos] = false;
+      if (pos < d.n_schedule) {
+        const int mu = d.schedule[pos];
+        int pi = 0, pj = 0, pT = 0;
+        ok[pos] = predecessor(d, mu, ci, cj, cT, k, &pi, &pj, &pT);
+        if (ok[pos]) {
+          const size_t q = pose_index(N, pi, pj, pT);
+          w[pos] = weight(d.B[q], d.edge_len[(size_t)mu * L + pT]);
+          vq[pos] = d.V[q];
+        }
       }
-      const uint32_t E = block_scan_sat(w, red32);
-      const uint32_t cand = sadd(sadd(vq, d.ct[mu]), E);
-      if (ok && cand != kInf) {
-        const uint64_t k2 = ((uint64_t)cand << 14) | ((uint64_t)pos << 11) | (uint64_t)k;
-        best = k2 < best ? k2 : best;
+    }
+    block_scan_sat<6>(w, red32);  // w[pos] becomes the edge sum E_k
+    uint64_t best = ~0ull;
+#pragma unroll
+    for (int pos = 0; pos < 6; pos++) {
+      if (pos < d.n_schedule) {
+        const uint32_t cand = sadd(sadd(vq[pos], d.ct[d.schedule[pos]]), w[pos]);
+        if (ok[pos] && cand != kInf) {
+          const uint64_t k2 = ((uint64_t)cand << 14) | ((uint64_t)pos << 11) | (uint64_t)k;
+          best = k2 < best ? k2 : best;
+        }
       }
     }
     best = block_min_u64(best, red64);
@@ -219,12 +249,32 @@ __global__ __launch_bounds__(kThreads) void extract_kernel(ExArgs x) {
   }
 }
 
+__global__ __launch_bounds__(kThreads) void extract_kernel(ExArgs x) {
+  __shared__ uint32_t red32[6][kWaves];
+  __shared__ uint64_t red64[kWaves];
+  extract_body(x, red32, red64);
+}
+
+// one workgroup per plan
+__global__ __launch_bounds__(kThreads) void extract_batch_kernel(const ExArgs* __restrict__ args) {
+  __shared__ uint32_t red32[6][kWaves];
+  __shared__ uint64_t red64[kWaves];
+  const ExArgs x = args[blockIdx.x];
+  extract_body(x, red32, red64);
+}
+
 }  // namespace
 
 hipError_t launch_extract(const DevPlan& d, uint32_t si, uint32_t sj, uint32_t st, uint32_t gi, uint32_t gj,
                           uint32_t gt, int radius, uint32_t w_xy, uint32_t w_t, hipStream_t s) {
   ExArgs x{d, si, sj, st, gi, gj, gt, radius, w_xy, w_t};
   hipLaunchKernelGGL(extract_kernel, dim3(1), dim3(kThreads), 0, s, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_batch(const ExArgs* d_args, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(extract_batch_kernel, dim3(n), dim3(kThreads), 0, s, d_args);
   return hipGetLastError();
 }
 

@@ -49,41 +49,87 @@ __device__ __forceinline__ uint32_t max_over(const uint8_t* __restrict__ src, co
   return m;
 }
 
+// One render job per plan; a block covers 256 columns of one row of one
+// plane: block -> (plane, row, column tile).
+__device__ __forceinline__ void render_pose(const RenderJob& r, int b, int& T, int& j, int& i) {
+  const int tiles = (r.N + 255) >> 8;
+  i = (b % tiles) * 256 + threadIdx.x;
+  j = (b / tiles) % r.N;
+  T = b / (tiles * r.N);
+}
+
+__device__ __forceinline__ int find_render_job(const RenderJob* __restrict__ jobs, int n_jobs, int t) {
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].first_block <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // side[T][j][i] = max over sideways samples of the walled image
-__global__ __launch_bounds__(256) void render_side_kernel(const uint8_t* __restrict__ image, uint8_t* __restrict__ side,
-                                                          const int32_t* __restrict__ taps, int N, int n_side) {
-  const int T = blockIdx.z;
-  const int j = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const uint32_t m = max_over<true>(image, taps + (size_t)T * 2 * kMaxTaps, n_side, i, j, N);
-  side[((size_t)T * N + j) * N + i] = (uint8_t)m;
+__device__ __forceinline__ void side_pose(const RenderJob& r, int b) {
+  int T, j, i;
+  render_pose(r, b, T, j, i);
+  if (i >= r.N) return;
+  const uint32_t m = max_over<true>(r.image, r.taps + (size_t)T * 2 * kMaxTaps, r.n_side, i, j, r.N);
+  r.side[((size_t)T * r.N + j) * r.N + i] = (uint8_t)m;
 }
 
 // B[T][j][i] = max over lengthwise samples of side[T]; walls forced hard
-__global__ __launch_bounds__(256) void render_len_kernel(const uint8_t* __restrict__ side, uint8_t* __restrict__ B,
-                                                         const int32_t* __restrict__ taps, int N, int n_side,
-                                                         int n_len) {
-  const int T = blockIdx.z;
-  const int j = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  uint32_t m = max_over<false>(side + (size_t)T * N * N, taps + (size_t)T * 2 * kMaxTaps + kMaxTaps, n_len, i, j, N);
+__device__ __forceinline__ void len_pose(const RenderJob& r, int b) {
+  int T, j, i;
+  render_pose(r, b, T, j, i);
+  if (i >= r.N) return;
+  const size_t NN = (size_t)r.N * r.N;
+  uint32_t m = max_over<false>(r.side + (size_t)T * NN, r.taps + (size_t)T * 2 * kMaxTaps + kMaxTaps, r.n_len, i, j,
+                               r.N);
   if (i == 0 || j == 0) m = kHard;
-  B[((size_t)T * N + j) * N + i] = (uint8_t)m;
+  r.B[(size_t)T * NN + (size_t)j * r.N + i] = (uint8_t)m;
+}
+
+__global__ __launch_bounds__(256) void render_side_kernel(RenderJob r) { side_pose(r, blockIdx.x); }
+__global__ __launch_bounds__(256) void render_len_kernel(RenderJob r) { len_pose(r, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void render_side_batch_kernel(const RenderJob* __restrict__ jobs, int n_jobs) {
+  const int k = find_render_job(jobs, n_jobs, blockIdx.x);
+  side_pose(jobs[k], blockIdx.x - jobs[k].first_block);
+}
+
+__global__ __launch_bounds__(256) void render_len_batch_kernel(const RenderJob* __restrict__ jobs, int n_jobs) {
+  const int k = find_render_job(jobs, n_jobs, blockIdx.x);
+  len_pose(jobs[k], blockIdx.x - jobs[k].first_block);
 }
 
 }  // namespace
 
 hipError_t launch_render(const DevPlan& d, const uint8_t* image, int n_side, int n_len, hipStream_t s) {
-  const int N = d.nx;
-  const dim3 block(256);
-  const dim3 grid((N + 255) / 256, N, d.nt);
-  uint8_t* side = reinterpret_cast<uint8_t*>(d.V);  // N_R bytes of the 4 N_R-byte value volume
-  hipLaunchKernelGGL(render_side_kernel, grid, block, 0, s, image, side, d.taps, N, n_side);
+  RenderJob r{};
+  r.image = image;
+  r.side = reinterpret_cast<uint8_t*>(d.V);  // N_R bytes of the 4 N_R-byte value volume
+  r.B = d.B;
+  r.taps = d.taps;
+  r.N = d.nx;
+  r.nt = d.nt;
+  r.n_side = n_side;
+  r.n_len = n_len;
+  r.blocks = ((d.nx + 255) / 256) * d.nx * d.nt;
+  hipLaunchKernelGGL(render_side_kernel, dim3(r.blocks), dim3(256), 0, s, r);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(render_len_kernel, grid, block, 0, s, side, d.B, d.taps, N, n_side, n_len);
+  hipLaunchKernelGGL(render_len_kernel, dim3(r.blocks), dim3(256), 0, s, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_batch(const RenderJob* d_jobs, int n_jobs, int total_blocks, hipStream_t s) {
+  if (n_jobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(render_side_batch_kernel, dim3(total_blocks), dim3(256), 0, s, d_jobs, n_jobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(render_len_batch_kernel, dim3(total_blocks), dim3(256), 0, s, d_jobs, n_jobs);
   return hipGetLastError();
 }
 

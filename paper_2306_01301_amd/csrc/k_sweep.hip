@@ -21,6 +21,9 @@
 //     paper's two loops around the circle), for straights the composition of
 //     the sections before it, starting from INF at the wall;
 //   * each wave replays its section from registers and stores.
+// A unit of work is a job (one maneuver of one plan); a batched launch
+// covers the tiles of many jobs, each block finding its job by a binary
+// search over the jobs' first block.
 // Turn curves and y-major straight lines put the 64 lanes on 64 consecutive
 // x of one row, so every load and store is a contiguous row segment.  The
 // x-major straight family (|tan| <= 1) puts the lanes on a column instead;
@@ -41,12 +44,6 @@ __device__ __forceinline__ uint32_t weight(uint32_t code, uint32_t base, uint32_
   return code == kHard ? kInf : w;
 }
 
-__device__ __forceinline__ uint32_t code_of(const uint32_t* packed, int k) {
-  return (packed[k >> 2] >> ((k & 3) * 8)) & 0xffu;
-}
-
-typedef uint16_t code2 __attribute__((ext_vector_type(2)));
-
 // Value volume access by 32-bit cell index.  The byte offset is formed in
 // 32 bits (volumes hold at most 2^30 poses), so the access is a uniform
 // 64-bit base plus a 32-bit per-lane offset (global_load ... saddr).
@@ -57,8 +54,6 @@ __device__ __forceinline__ void st_value(uint32_t* V, uint32_t cell, uint32_t v)
   *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(V) + (cell << 2)) = v;
 }
 
-__device__ __forceinline__ uint32_t code_of(const code2* packed, int k) { return packed[k >> 1][k & 1]; }
-
 // Workgroup index spread over the 8 XCDs so that consecutive tiles (which
 // share row segments at their edges) land on the same XCD and its L2.
 __device__ __forceinline__ int xcd_tile(int b, int n) {
@@ -66,26 +61,12 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
-// Workgroup barrier that waits only for this wave's LDS operations, not for
-// its outstanding global loads (__syncthreads waits for both), so loads
-// issued for the next chunk stay in flight across it.
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-struct SweepArgs {
-  uint32_t* V;
-  const uint8_t* B;
-  int N;       // cells per side
-  int L;       // curve length (N_theta for turns, N for straights)
-  uint32_t ct;
-};
-
-// Value entering this wave's section: cyclic fixed point (turns) or the
+// Value entering this wave's section: the cyclic fixed point (turns) or the
 // composition of the earlier sections from INF (straights).
-template <bool CYCLIC>
-__device__ __forceinline__ uint32_t section_carry(const uint32_t (*aggD)[64], const uint32_t (*aggC)[64],
-                                                  int S, int wave, int lane) {
+__device__ __forceinline__ uint32_t section_carry(const uint32_t (*aggD)[64], const uint32_t (*aggC)[64], int S,
+                                                  int wave, int lane, bool cyclic) {
   uint32_t C = kInf;
-  if (CYCLIC) {
+  if (cyclic) {
     int s = wave;
     for (int t = 0; t < S; t++) {
       C = umin(sadd(C, aggD[s][lane]), aggC[s][lane]);
@@ -97,128 +78,125 @@ __device__ __forceinline__ uint32_t section_carry(const uint32_t (*aggD)[64], co
   return C;
 }
 
-// Row-coalesced sweep: turns (CYCLIC) and y-major straights.
-//   turns:     block -> (x tile, y'); step k -> plane T_k, offsets (ox, oy)
-//   straights: block -> (x tile, plane); step k -> row c_k, column x' + B(c_k)
-template <int P, bool CYCLIC>
-__global__ __launch_bounds__(1024) void row_sweep_kernel(SweepArgs a, const int32_t* __restrict__ offx,
-                                                        const int32_t* __restrict__ offy, int asc,
-                                                        uint32_t lq_base, uint32_t lq4,
-                                                        // straights only:
-                                                        const int16_t* __restrict__ skew,
-                                                        const int32_t* __restrict__ planes,
-                                                        const uint32_t* __restrict__ edge_len,
-                                                        const int32_t* __restrict__ fwd, int mu_forward) {
-  __shared__ uint32_t aggD[16][64];
-  __shared__ uint32_t aggC[16][64];
-  __shared__ uint32_t wlut[256];  // edge weight by obstacle code (INF for hard)
-  const int S = blockDim.x >> 6;
+struct RowShared {
+  uint32_t aggD[16][64];
+  uint32_t aggC[16][64];
+  uint32_t wlut[256];      // edge weight by obstacle code (INF for hard)
+  uint32_t row_base[1024]; // per step: index of the first pose of the row it reads
+  uint16_t shift[1024];    // per step: column offset of curve x' (reduced mod N)
+};
+
+// Row-coalesced sweep of one tile (64 curves) of a job: turns (cyclic) and
+// y-major straights.
+//   turns:     tile -> (x tile, y'); step k -> plane T_k, offsets (ox, oy)
+//   straights: tile -> (x tile, plane slot); step k -> row c_k, column x' + B(c_k)
+template <int P>
+__device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowShared& sh) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int N = a.N, L = a.L;
-  const int tiles_x = (N + 63) >> 6;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tx = tile % tiles_x;
-  const int outer = tile / tiles_x;  // y' (turns) or plane slot (straights)
+  const bool cyclic = a.cyclic != 0;
+  const int S = (L + P - 1) / P;  // sections of this job (the workgroup may hold more waves)
+  const bool busy = wave < S;
+  const int tx = tile % a.tiles_x;
+  const int outer = tile / a.tiles_x;  // y' (turns) or plane slot (straights)
   const int xp = tx * 64 + lane;
   const bool active = xp < N;
 
   int T0 = 0;
-  uint32_t base = lq_base, l4 = lq4;
-  int dir = asc;
+  uint32_t Lq = a.lq;
+  int dir = a.dir;
   const int16_t* sk = nullptr;
-  if (!CYCLIC) {
-    T0 = planes[outer];
-    const uint32_t Lq = edge_len[T0];
-    base = 256u * Lq + 128u;
-    l4 = 4u * Lq;
-    dir = (fwd[T0] > 0) == (mu_forward != 0);
-    sk = skew + (size_t)T0 * N;
+  if (!cyclic) {
+    T0 = a.planes[outer];
+    Lq = a.edge_len[T0];
+    dir = (a.fwd[T0] > 0) == (a.mu_forward != 0);
+    sk = a.skew + (size_t)T0 * N;
   }
-  for (int c = threadIdx.x; c < 256; c += blockDim.x) wlut[c] = weight((uint32_t)c, base, l4);
-
-  uint32_t u[P];
-  uint32_t code[P];
-
-  // Step k of this wave's section touches row `row` of plane T, columns
-  // (xp + shift) mod N: a uniform row base plus a small per-lane column.
-  // Sections are P steps; steps past the curve length (when S P > L) are
-  // identity maps that touch no memory.
-  auto step_geometry = [&](int k, int& T, int& row, int& shift) {
-    int step = wave * P + k;
-    step = step < L ? step : L - 1;
-    if (CYCLIC) {
-      T = dir ? step : (L - 1 - step);
-      shift = offx[T];
-      row = outer + offy[T];
+  for (int c = threadIdx.x; c < 256; c += blockDim.x) sh.wlut[c] = weight((uint32_t)c, 256u * Lq + 128u, 4u * Lq);
+  // Step s of a curve touches row `row` of plane T at column (x' + shift)
+  // mod N: a row base shared by the 64 lanes plus a small per-lane column.
+  // The geometry of all steps goes to LDS once per workgroup.
+  for (int s = threadIdx.x; s < L; s += blockDim.x) {
+    int T, row, shift;
+    if (cyclic) {
+      T = dir ? s : (L - 1 - s);
+      shift = a.offx[T];
+      row = outer + a.offy[T];
       row -= (row >= N) ? N : 0;
     } else {
       T = T0;
-      const int c = dir ? step : (L - 1 - step);
+      const int c = dir ? s : (L - 1 - s);
       shift = sk[c];
       shift += (shift < 0) ? N : 0;
       row = c;
     }
-  };
-  const int n_real = (L - wave * P) < P ? (L - wave * P) : P;  // real steps of this wave
-
-  // Load this wave's section of the 64 curves.  Lanes past the grid edge
-  // read a valid cell, so the loads carry no branch.
-  const int xl = active ? xp : N - 1;
-#pragma unroll
-  for (int k = 0; k < P; k++) {
-    int T, row, shift;
-    step_geometry(k, T, row, shift);
-    const uint32_t rbase = ((uint32_t)T * (uint32_t)N + (uint32_t)row) * (uint32_t)N;
-    int i = xl + shift;
-    i -= (i >= N) ? N : 0;
-    // lanes are independent curves: an idle lane computes on its clamped
-    // cell and never stores, so loaded values need no masking
-    const uint32_t cell = rbase + (uint32_t)i;
-    u[k] = ld_value(a.V, cell);
-    code[k] = a.B[cell];
+    sh.row_base[s] = ((uint32_t)T * (uint32_t)N + (uint32_t)row) * (uint32_t)N;
+    sh.shift[s] = (uint16_t)shift;
   }
+  __syncthreads();  // weight table and geometry ready
 
-  __syncthreads();  // weight table ready
-  // weights replace the codes in place; compose the section into (D, C):
-  // min(C + w, u + ct + w) = min(C, u + ct) + w (saturating add is monotone)
-  uint32_t D = 0, C = kInf;
+  uint32_t u[P];
+  uint32_t code[P];
+  // Sections are P steps; steps past the curve length (when S P > L) are
+  // identity maps that touch no memory.
+  const int n_real = (L - wave * P) < P ? (L - wave * P) : P;  // real steps of this wave
+  const int first = wave * P;
+
+  if (busy) {
+    // Load this wave's section of the 64 curves.  Lanes past the grid edge
+    // read a valid cell, so the loads carry no branch; lanes are independent
+    // curves, so an idle lane's values are never stored.
+    const int xl = active ? xp : N - 1;
 #pragma unroll
-  for (int k = 0; k < P; k++) code[k] = wlut[code[k]];
-#pragma unroll
-  for (int k = 0; k < P; k++) {
-    if (k < n_real) {
-      C = sadd(umin(C, sadd(u[k], a.ct)), code[k]);
-      D = sadd(D, code[k]);
+    for (int k = 0; k < P; k++) {
+      const int s = (first + k) < L ? first + k : L - 1;
+      int i = xl + (int)sh.shift[s];
+      i -= (i >= N) ? N : 0;
+      const uint32_t cell = sh.row_base[s] + (uint32_t)i;
+      u[k] = ld_value(a.V, cell);
+      code[k] = a.B[cell];
     }
   }
-  aggD[wave][lane] = D;
-  aggC[wave][lane] = C;
-  __syncthreads();
-  uint32_t v = section_carry<CYCLIC>(aggD, aggC, S, wave, lane);
-
-  // replay: a hard pose has weight INF, and w >> 31 (arithmetic) is then all
-  // ones, which forces its output to INF
+  if (busy) {
+    // weights replace the codes; compose the section into (D, C):
+    // min(C + w, u + ct + w) = min(C, u + ct) + w (saturating add is monotone)
+    uint32_t D = 0, C = kInf;
 #pragma unroll
-  for (int k = 0; k < P; k++) {
-    const uint32_t w = code[k];
-    const uint32_t uu = u[k];
-    u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
-    v = sadd(umin(v, sadd(uu, a.ct)), w);
-  }
-  // recompute the column of every step rather than keeping P of them live
-  int xs = xp;
-  asm volatile("" : "+v"(xs));
-  if (active) {
+    for (int k = 0; k < P; k++) code[k] = sh.wlut[code[k]];
 #pragma unroll
     for (int k = 0; k < P; k++) {
       if (k < n_real) {
-        int T, row, shift;
-        step_geometry(k, T, row, shift);
-        const uint32_t rbase = ((uint32_t)T * (uint32_t)N + (uint32_t)row) * (uint32_t)N;
-        int i = xs + shift;
-        i -= (i >= N) ? N : 0;
-        st_value(a.V, rbase + (uint32_t)i, u[k]);
+        C = sadd(umin(C, sadd(u[k], a.ct)), code[k]);
+        D = sadd(D, code[k]);
+      }
+    }
+    sh.aggD[wave][lane] = D;
+    sh.aggC[wave][lane] = C;
+  }
+  __syncthreads();
+  if (busy) {
+    uint32_t v = section_carry(sh.aggD, sh.aggC, S, wave, lane, cyclic);
+    // replay: a hard pose has weight INF, and w >> 31 (arithmetic) is then
+    // all ones, which forces its output to INF
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+      const uint32_t w = code[k];
+      const uint32_t uu = u[k];
+      u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+      v = sadd(umin(v, sadd(uu, a.ct)), w);
+    }
+    // recompute the column of every step rather than keeping P of them live
+    int xs = xp;
+    asm volatile("" : "+v"(xs));
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < P; k++) {
+        if (k < n_real) {
+          int i = xs + (int)sh.shift[first + k];
+          i -= (i >= N) ? N : 0;
+          st_value(a.V, sh.row_base[first + k] + (uint32_t)i, u[k]);
+        }
       }
     }
   }
@@ -234,40 +212,45 @@ __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepArgs a, const int3
 // LDS, carry from the previous chunk), write the results back into the tile,
 // and the tile is stored row by row.
 template <int Q>
-__global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const int16_t* __restrict__ skew,
-                                                          const int32_t* __restrict__ planes,
-                                                          const uint32_t* __restrict__ edge_len,
-                                                          const int32_t* __restrict__ fwd, int mu_forward) {
-  constexpr int LINES = 64;
-  constexpr int R = LINES + Q;        // rows a chunk can touch (|B(c+1) - B(c)| <= 1)
-  constexpr int PITCH = Q + 1;        // odd pitch: a column read by 64 lanes hits 64 banks
-  constexpr int SUB = Q / 4;          // columns per wave
-  constexpr int ITER = (R * Q + 255) / 256;
+struct XShared {
+  static constexpr int LINES = 64;
+  static constexpr int R = LINES + Q;  // rows a chunk can touch (|B(c+1) - B(c)| <= 1)
+  static constexpr int PITCH = Q + 1;  // odd pitch: a column read by 64 lanes hits 64 banks
+  uint32_t tV[R * PITCH];
+  uint8_t tB[R * PITCH];
+  int32_t tS[Q];
+  uint32_t aggD[4][64];
+  uint32_t aggC[4][64];
+  uint32_t wlut[256];
+  int16_t skew[1024];  // B(c, T) of this plane
+};
+
+template <int Q>
+__device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, XShared<Q>& sh) {
+  using X = XShared<Q>;
+  constexpr int LINES = X::LINES, PITCH = X::PITCH;
+  constexpr int SUB = Q / 4;  // columns per wave
+  constexpr int ITER = (X::R * Q + 255) / 256;
   static_assert(256 % Q == 0, "Q must divide 256");
-  __shared__ uint32_t tV[R * PITCH];
-  __shared__ uint8_t tB[R * PITCH];
-  __shared__ int32_t tS[Q];
-  __shared__ uint32_t aggD[4][64];
-  __shared__ uint32_t aggC[4][64];
-  __shared__ uint32_t wlut[256];
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int N = a.N;
-  const int tiles_x = (N + LINES - 1) / LINES;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int x0 = (tile % tiles_x) * LINES;
-  const int T = planes[tile / tiles_x];
+  const int x0 = (tile % a.tiles_x) * LINES;
+  const int T = a.planes[tile / a.tiles_x];
   const uint32_t plane = (uint32_t)T * (uint32_t)N * (uint32_t)N;
-  const uint32_t Lq = edge_len[T];
-  wlut[tid] = weight((uint32_t)tid, 256u * Lq + 128u, 4u * Lq);
-  const int dir = (fwd[T] > 0) == (mu_forward != 0);
-  const int16_t* sk = skew + (size_t)T * N;
-  const int kk = tid % Q;       // column of this thread in the load/store phases
-  const int r0 = tid / Q;       // first row of this thread; rows r0 + it * (256 / Q)
+  const uint32_t Lq = a.edge_len[T];
+  sh.wlut[tid] = weight((uint32_t)tid, 256u * Lq + 128u, 4u * Lq);
+  const int dir = (a.fwd[T] > 0) == (a.mu_forward != 0);
+  const int16_t* skg = a.skew + (size_t)T * N;
+  for (int c = tid; c < N; c += 256) sh.skew[c] = skg[c];
+  __syncthreads();
+  const int16_t* sk = sh.skew;
+  const int kk = tid % Q;  // column of this thread in the load/store phases
+  const int r0 = tid / Q;  // first row of this thread; rows r0 + it * (256 / Q)
   const bool line_ok = x0 + lane < N;
 
-  uint32_t carry = kInf;        // value carried along line x0 + lane into the chunk
+  uint32_t carry = kInf;  // value carried along line x0 + lane into the chunk
   for (int k0 = 0; k0 < N; k0 += Q) {
     const int nq = (N - k0) < Q ? (N - k0) : Q;
     const int c_first = dir ? k0 : (N - 1 - k0);
@@ -280,7 +263,7 @@ __global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const in
     const int my_c = dir ? (k0 + kk) : (N - 1 - (k0 + kk));
     const bool col_ok = kk < nq;
     const int my_b = col_ok ? (int)sk[my_c] : 0;
-    if (tid < Q) tS[tid] = my_b;
+    if (tid < Q) sh.tS[tid] = my_b;
 
     // load the band: every owned cell once, rows as contiguous segments
     uint32_t lv[ITER], lc[ITER];
@@ -301,8 +284,8 @@ __global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const in
     for (int it = 0; it < ITER; it++) {
       if (own[it]) {
         const int r = r0 + it * (256 / Q);
-        tV[r * PITCH + kk] = lv[it];
-        tB[r * PITCH + kk] = (uint8_t)lc[it];
+        sh.tV[r * PITCH + kk] = lv[it];
+        sh.tB[r * PITCH + kk] = (uint8_t)lc[it];
       }
     }
     __syncthreads();
@@ -314,9 +297,9 @@ __global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const in
     for (int q = 0; q < SUB; q++) {
       const int kq = wave * SUB + q;
       const bool ok = kq < nq;
-      rr[q] = ok ? lane + tS[kq] - bmin : 0;  // in [0, rows) for real columns
-      u[q] = ok ? tV[rr[q] * PITCH + kq] : kInf;
-      w[q] = ok ? wlut[tB[rr[q] * PITCH + kq]] : 0u;
+      rr[q] = ok ? lane + sh.tS[kq] - bmin : 0;  // in [0, rows) for real columns
+      u[q] = ok ? sh.tV[rr[q] * PITCH + kq] : kInf;
+      w[q] = ok ? sh.wlut[sh.tB[rr[q] * PITCH + kq]] : 0u;
     }
     uint32_t D = 0, C = kInf;
 #pragma unroll
@@ -325,20 +308,20 @@ __global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const in
       C = ok ? sadd(umin(C, sadd(u[q], a.ct)), w[q]) : C;
       D = sadd(D, w[q]);
     }
-    aggD[wave][lane] = D;
-    aggC[wave][lane] = C;
+    sh.aggD[wave][lane] = D;
+    sh.aggC[wave][lane] = C;
     __syncthreads();
     uint32_t v = carry;
-    for (int s = 0; s < wave; s++) v = umin(sadd(v, aggD[s][lane]), aggC[s][lane]);
+    for (int s = 0; s < wave; s++) v = umin(sadd(v, sh.aggD[s][lane]), sh.aggC[s][lane]);
 #pragma unroll
     for (int q = 0; q < SUB; q++) {
       const int kq = wave * SUB + q;
       if (kq < nq && line_ok) {
-        tV[rr[q] * PITCH + kq] = umin(v, u[q]) | (uint32_t)((int32_t)w[q] >> 31);
+        sh.tV[rr[q] * PITCH + kq] = umin(v, u[q]) | (uint32_t)((int32_t)w[q] >> 31);
         v = sadd(umin(v, sadd(u[q], a.ct)), w[q]);
       }
     }
-    for (int s = 0; s < 4; s++) carry = umin(sadd(carry, aggD[s][lane]), aggC[s][lane]);
+    for (int s = 0; s < 4; s++) carry = umin(sadd(carry, sh.aggD[s][lane]), sh.aggC[s][lane]);
     __syncthreads();
 
     // store the band back
@@ -346,11 +329,55 @@ __global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepArgs a, const in
     for (int it = 0; it < ITER; it++) {
       if (own[it]) {
         const int r = r0 + it * (256 / Q);
-        st_value(a.V, cell[it], tV[r * PITCH + kk]);
+        st_value(a.V, cell[it], sh.tV[r * PITCH + kk]);
       }
     }
     __syncthreads();
   }
+}
+
+// The job a block of a batched launch works on: jobs are listed in order of
+// their first block, so a binary search over `first_block` finds it.
+__device__ __forceinline__ int find_job(const SweepJob* __restrict__ jobs, int n_jobs, int t) {
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].first_block <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int P>
+__global__ __launch_bounds__(1024) void row_sweep_kernel(SweepJob job) {
+  __shared__ RowShared sh;
+  row_sweep_tile<P>(job, xcd_tile(blockIdx.x, gridDim.x), sh);
+}
+
+template <int P>
+__global__ __launch_bounds__(1024) void row_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs) {
+  __shared__ RowShared sh;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
+  const SweepJob job = jobs[j];
+  row_sweep_tile<P>(job, t - job.first_block, sh);
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepJob job) {
+  __shared__ XShared<Q> sh;
+  xmajor_sweep_tile<Q>(job, xcd_tile(blockIdx.x, gridDim.x), sh);
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void xmajor_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs) {
+  __shared__ XShared<Q> sh;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
+  const SweepJob job = jobs[j];
+  xmajor_sweep_tile<Q>(job, t - job.first_block, sh);
 }
 
 __global__ void init_kernel(uint32_t* __restrict__ V, size_t n4, uint32_t start) {
@@ -369,6 +396,27 @@ __global__ void init_kernel(uint32_t* __restrict__ V, size_t n4, uint32_t start)
   }
 }
 
+// Batched init: job k fills V of plan k (n4[k] uint4 words, start index
+// start[k]); blocks stride over all plans' words.
+__global__ void init_batch_kernel(const InitJob* __restrict__ jobs, int n_jobs) {
+  for (int k = 0; k < n_jobs; k++) {
+    const InitJob j = jobs[k];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < j.n4; q += stride) {
+      const size_t e = q * 4;
+      uint4 v = make_uint4(kInf, kInf, kInf, kInf);
+      if (j.start >= e && j.start < e + 4) {
+        const uint32_t o = (uint32_t)(j.start - e);
+        if (o == 0) v.x = 0;
+        if (o == 1) v.y = 0;
+        if (o == 2) v.z = 0;
+        if (o == 3) v.w = 0;
+      }
+      reinterpret_cast<uint4*>(j.V)[q] = v;
+    }
+  }
+}
+
 __global__ void walls_kernel(uint8_t* __restrict__ B, int N, int L) {
   // one block per plane: row j = 0 and column i = 0 are hard
   const size_t base = (size_t)blockIdx.x * N * N;
@@ -378,43 +426,78 @@ __global__ void walls_kernel(uint8_t* __restrict__ B, int N, int L) {
   }
 }
 
-// Steps per wave: the smallest power of two in [8, 64] that splits the curve
-// into at most 16 sections (16 waves of a 1024-thread workgroup).
 constexpr int XQ = 32;  // columns per x-major chunk
 
+}  // namespace
+
+// Steps per wave: the smallest power of two in [8, 64] that splits the curve
+// into at most 16 sections (16 waves of a 1024-thread workgroup).
 int pick_section(int len) {
   int P = 8;
   while (P < 64 && P * 16 < len) P <<= 1;
   return (P * 16 >= len) ? P : 0;
 }
 
-template <bool CYCLIC>
-hipError_t launch_row(int P, dim3 grid, dim3 block, hipStream_t s, SweepArgs a, const int32_t* offx,
-                      const int32_t* offy, int asc, uint32_t base, uint32_t l4, const int16_t* skew,
-                      const int32_t* planes, const uint32_t* edge_len, const int32_t* fwd, int mu_fwd) {
-  switch (P) {
-    case 64:
-      hipLaunchKernelGGL((row_sweep_kernel<64, CYCLIC>), grid, block, 0, s, a, offx, offy, asc, base, l4, skew, planes,
-                         edge_len, fwd, mu_fwd);
-      break;
-    case 32:
-      hipLaunchKernelGGL((row_sweep_kernel<32, CYCLIC>), grid, block, 0, s, a, offx, offy, asc, base, l4, skew, planes,
-                         edge_len, fwd, mu_fwd);
-      break;
-    case 16:
-      hipLaunchKernelGGL((row_sweep_kernel<16, CYCLIC>), grid, block, 0, s, a, offx, offy, asc, base, l4, skew, planes,
-                         edge_len, fwd, mu_fwd);
-      break;
-    case 8:
-      hipLaunchKernelGGL((row_sweep_kernel<8, CYCLIC>), grid, block, 0, s, a, offx, offy, asc, base, l4, skew, planes,
-                         edge_len, fwd, mu_fwd);
-      break;
+// The jobs of one maneuver of one plan: a row job (turns, or the y-major
+// straight planes) and, for straights, an x-major job.  Returns the number of
+// jobs written (0..2); blocks counts each job's workgroups.
+int make_sweep_jobs(const DevPlan& d, int mu, SweepJob* row, SweepJob* xmaj) {
+  const int N = d.nx, L = d.nt;
+  const int tiles_x = (N + 63) / 64;
+  SweepJob j{};
+  j.V = d.V;
+  j.B = d.B;
+  j.N = N;
+  j.ct = d.ct[mu];
+  j.tiles_x = tiles_x;
+  int n = 0;
+  if (mu == NHP_SF || mu == NHP_SB) {
+    j.L = N;
+    j.cyclic = 0;
+    j.skew = d.skew;
+    j.edge_len = d.edge_len + (size_t)mu * L;
+    j.fwd = d.fwd;
+    j.mu_forward = (mu == NHP_SF);
+    j.P = pick_section(N);
+    SweepJob y = j, x = j;
+    y.planes = d.planes + d.n_planes_x;
+    y.blocks = tiles_x * d.n_planes_y;
+    x.planes = d.planes;
+    x.blocks = tiles_x * d.n_planes_x;
+    x.P = 0;
+    row->blocks = 0;
+    xmaj->blocks = 0;
+    if (y.blocks) *row = y;
+    if (x.blocks) *xmaj = x;
+    n = (y.blocks > 0) + (x.blocks > 0);
+  } else {
+    const bool left = (mu == NHP_LF || mu == NHP_LB);
+    j.L = L;
+    j.cyclic = 1;
+    j.dir = (mu == NHP_LF || mu == NHP_RB);  // eqs. (25)-(28): LF and RB step to T+1
+    j.offx = d.turn_off + (left ? 0 : 2) * L;
+    j.offy = d.turn_off + (left ? 1 : 3) * L;
+    j.lq = d.turn_lq[mu];
+    j.P = pick_section(L);
+    j.blocks = tiles_x * N;
+    *row = j;
+    xmaj->blocks = 0;
+    n = 1;
+  }
+  return n;
+}
+
+hipError_t launch_row_job(const SweepJob& j, hipStream_t s) {
+  const dim3 grid(j.blocks), block(64 * ((j.L + j.P - 1) / j.P));
+  switch (j.P) {
+    case 64: hipLaunchKernelGGL(row_sweep_kernel<64>, grid, block, 0, s, j); break;
+    case 32: hipLaunchKernelGGL(row_sweep_kernel<32>, grid, block, 0, s, j); break;
+    case 16: hipLaunchKernelGGL(row_sweep_kernel<16>, grid, block, 0, s, j); break;
+    case 8: hipLaunchKernelGGL(row_sweep_kernel<8>, grid, block, 0, s, j); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
-
-}  // namespace
 
 hipError_t launch_init(const DevPlan& d, uint32_t start_index, hipStream_t s) {
   const size_t NR = (size_t)d.nx * d.nx * d.nt;  // a multiple of 64: nx and nt are multiples of 8
@@ -425,45 +508,50 @@ hipError_t launch_init(const DevPlan& d, uint32_t start_index, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_init_batch(const InitJob* d_jobs, int n_jobs, size_t max_n4, hipStream_t s) {
+  size_t blocks = (max_n4 + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(init_batch_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, n_jobs);
+  return hipGetLastError();
+}
+
 hipError_t launch_force_walls(const DevPlan& d, hipStream_t s) {
   hipLaunchKernelGGL(walls_kernel, dim3(d.nt), dim3(256), 0, s, d.B, d.nx, d.nt);
   return hipGetLastError();
 }
 
 hipError_t launch_sweep(const DevPlan& d, int mu, hipStream_t s) {
-  const int N = d.nx, L = d.nt;
-  const int tiles_x = (N + 63) / 64;
-  SweepArgs a{d.V, d.B, N, L, d.ct[mu]};
-  if (mu == NHP_SF || mu == NHP_SB) {
-    const int P = pick_section(N);
-    if (!P) return hipErrorInvalidValue;
-    const int S = (N + P - 1) / P;
-    a.L = N;
-    const int mu_fwd = (mu == NHP_SF);
-    const uint32_t* el = d.edge_len + (size_t)mu * L;
-    hipError_t e = hipSuccess;
-    if (d.n_planes_y > 0) {
-      e = launch_row<false>(P, dim3(tiles_x * d.n_planes_y), dim3(64 * S), s, a, nullptr, nullptr, 0, 0, 0, d.skew,
-                            d.planes + d.n_planes_x, el, d.fwd, mu_fwd);
-      if (e != hipSuccess) return e;
-    }
-    if (d.n_planes_x > 0) {
-      hipLaunchKernelGGL((xmajor_sweep_kernel<XQ>), dim3(tiles_x * d.n_planes_x), dim3(256), 0, s, a, d.skew,
-                         d.planes, el, d.fwd, mu_fwd);
-      e = hipGetLastError();
-    }
-    return e;
+  SweepJob row{}, xmaj{};
+  make_sweep_jobs(d, mu, &row, &xmaj);
+  if (row.blocks) {
+    if (!row.P) return hipErrorInvalidValue;
+    const hipError_t e = launch_row_job(row, s);
+    if (e != hipSuccess) return e;
   }
-  const int P = pick_section(L);
-  if (!P) return hipErrorInvalidValue;
-  const int S = (L + P - 1) / P;
-  const bool left = (mu == NHP_LF || mu == NHP_LB);
-  const int asc = (mu == NHP_LF || mu == NHP_RB);  // eqs. (25)-(28): LF, RB step to T+1
-  const int32_t* offx = d.turn_off + (left ? 0 : 2) * L;
-  const int32_t* offy = d.turn_off + (left ? 1 : 3) * L;
-  const uint32_t Lq = d.turn_lq[mu];
-  return launch_row<true>(P, dim3(tiles_x * N), dim3(64 * S), s, a, offx, offy, asc, 256u * Lq + 128u, 4u * Lq,
-                          nullptr, nullptr, nullptr, nullptr, 0);
+  if (xmaj.blocks) {
+    hipLaunchKernelGGL((xmajor_sweep_kernel<XQ>), dim3(xmaj.blocks), dim3(256), 0, s, xmaj);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool xmajor,
+                              hipStream_t s) {
+  if (n_jobs == 0) return hipSuccess;
+  const dim3 grid(total_blocks);
+  if (xmajor) {
+    hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ>), grid, dim3(256), 0, s, d_jobs, n_jobs);
+    return hipGetLastError();
+  }
+  const dim3 block(1024);
+  switch (P) {
+    case 64: hipLaunchKernelGGL(row_sweep_batch_kernel<64>, grid, block, 0, s, d_jobs, n_jobs); break;
+    case 32: hipLaunchKernelGGL(row_sweep_batch_kernel<32>, grid, block, 0, s, d_jobs, n_jobs); break;
+    case 16: hipLaunchKernelGGL(row_sweep_batch_kernel<16>, grid, block, 0, s, d_jobs, n_jobs); break;
+    case 8: hipLaunchKernelGGL(row_sweep_batch_kernel<8>, grid, block, 0, s, d_jobs, n_jobs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace nhp

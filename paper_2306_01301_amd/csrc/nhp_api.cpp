@@ -12,21 +12,6 @@
 using nhp::DevPlan;
 using nhp::HostTables;
 
-struct nhp_plan {
-  nhp_params p{};
-  hipStream_t stream = nullptr;
-  int device = 0;
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  bool own_ws = false;
-  HostTables t;
-  DevPlan d{};
-  bool has_cspace = false;
-  bool has_value = false;
-  uint32_t start[3] = {0, 0, 0};
-  int front = -1, rear = -1, half_width = -1;  // box of the last render (taps cached)
-};
-
 namespace {
 
 thread_local char g_err[512] = "";
@@ -44,6 +29,20 @@ int ok() {
   g_err[0] = 0;
   return NHP_OK;
 }
+
+}  // namespace
+
+int nhp::set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int nhp::clear_error() { return ok(); }
+
+namespace {
 
 int hip_fail(hipError_t e, const char* what) {
   return fail(NHP_EHIP, "%s: %s", what, hipGetErrorString(e));
@@ -212,6 +211,7 @@ int plan_create(const nhp_params* params, void* d_workspace, size_t workspace_by
 int plan_destroy(nhp_plan* plan) {
   if (!plan) return ok();
   (void)hipStreamSynchronize(plan->stream);
+  if (plan->cycle) (void)hipGraphExecDestroy(plan->cycle);
   if (plan->own_ws && plan->ws) (void)hipFree(plan->ws);
   delete plan;
   return ok();
@@ -231,24 +231,37 @@ int render_cspace(nhp_plan* plan, const uint8_t* d_image, int32_t front, int32_t
   if (front < 0 || rear < 0 || half_width < 0 || front > 255 || rear > 255 || half_width > 255)
     return fail(NHP_EINVAL, "box extents must be 0..255 cells");
   const int n_side = 2 * half_width + 1, n_len = front + rear + 1;
-  if (front != plan->front || rear != plan->rear || half_width != plan->half_width) {
-    const int L = (int)plan->p.ntheta;
-    std::vector<int32_t> taps((size_t)L * 2 * nhp::kMaxTaps, 0);
-    for (int T = 0; T < L; T++)
-      nhp::render_taps_host(plan->p, plan->t, T, front, rear, half_width, &taps[(size_t)T * 2 * nhp::kMaxTaps],
-                            &taps[(size_t)T * 2 * nhp::kMaxTaps + nhp::kMaxTaps]);
-    HIP_CHECK(hipMemcpyAsync(plan->d.taps, taps.data(), taps.size() * 4, hipMemcpyHostToDevice, plan->stream),
-              "tap upload");
-    HIP_CHECK(hipStreamSynchronize(plan->stream), "tap upload");
-    plan->front = front;
-    plan->rear = rear;
-    plan->half_width = half_width;
-  }
+  rc = nhp::upload_taps(plan, front, rear, half_width);
+  if (rc) return rc;
   HIP_CHECK(nhp::launch_render(plan->d, d_image, n_side, n_len, plan->stream), "render_cspace launch");
   plan->has_cspace = true;
   plan->has_value = false;
   return ok();
 }
+
+}  // extern "C"
+
+// Uploads the footprint sample offsets of every plane for a vehicle box
+// (kept while the box does not change).
+int nhp::upload_taps(nhp_plan* plan, int front, int rear, int half_width) {
+  if (front < 0 || rear < 0 || half_width < 0 || front > 255 || rear > 255 || half_width > 255)
+    return fail(NHP_EINVAL, "box extents must be 0..255 cells");
+  if (front == plan->front && rear == plan->rear && half_width == plan->half_width) return NHP_OK;
+  const int L = (int)plan->p.ntheta;
+  std::vector<int32_t> taps((size_t)L * 2 * nhp::kMaxTaps, 0);
+  for (int T = 0; T < L; T++)
+    nhp::render_taps_host(plan->p, plan->t, T, front, rear, half_width, &taps[(size_t)T * 2 * nhp::kMaxTaps],
+                          &taps[(size_t)T * 2 * nhp::kMaxTaps + nhp::kMaxTaps]);
+  HIP_CHECK(hipMemcpyAsync(plan->d.taps, taps.data(), taps.size() * 4, hipMemcpyHostToDevice, plan->stream),
+            "sample offset upload");
+  HIP_CHECK(hipStreamSynchronize(plan->stream), "sample offset upload");
+  plan->front = front;
+  plan->rear = rear;
+  plan->half_width = half_width;
+  return NHP_OK;
+}
+
+extern "C" {
 
 int plan_set_cspace(nhp_plan* plan, const uint8_t* d_cspace) {
   int rc = check_plan(plan);
@@ -262,10 +275,39 @@ int plan_set_cspace(nhp_plan* plan, const uint8_t* d_cspace) {
   return ok();
 }
 
+// Captures one cycle of the schedule (all its launches) into a graph on a
+// private stream; the graph depends only on the plan's fixed device state,
+// so it is replayed on whatever stream the plan uses.
+static void capture_cycle(nhp_plan* plan) {
+  hipStream_t cs = nullptr;
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    for (int k = 0; k < plan->p.n_schedule; k++)
+      ok = ok && nhp::launch_sweep(plan->d, plan->p.schedule[k], cs) == hipSuccess;
+    ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok && g != nullptr;
+  }
+  if (ok) ok = hipGraphInstantiate(&plan->cycle, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (!ok) {
+    plan->cycle = nullptr;
+    plan->graph_failed = true;
+    (void)hipGetLastError();  // clear a sticky capture error
+  }
+}
+
 static int run_cycles(nhp_plan* plan, uint32_t n_cycles) {
-  for (uint32_t n = 0; n < n_cycles; n++)
+  if (n_cycles > 1 && !plan->cycle && !plan->graph_failed) capture_cycle(plan);
+  for (uint32_t n = 0; n < n_cycles; n++) {
+    if (plan->cycle) {
+      HIP_CHECK(hipGraphLaunch(plan->cycle, plan->stream), "cycle graph launch");
+      continue;
+    }
     for (int k = 0; k < plan->p.n_schedule; k++)
       HIP_CHECK(nhp::launch_sweep(plan->d, plan->p.schedule[k], plan->stream), "sweep launch");
+  }
   return NHP_OK;
 }
 

@@ -1,0 +1,363 @@
+// nhp_batch.cpp -- batched launches over many plans: one launch per pass
+// covers the current maneuver of every plan in the batch (tiles of all plans
+// in one grid), so small plans fill the GPU together and a plan that joins
+// later runs alongside plans that are further along (continuous batching).
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "nhp_internal.h"
+
+namespace {
+
+constexpr int kSlots = 4;  // job tables in flight (ring), each reused only after its launches finished
+
+struct Slot {
+  void* host = nullptr;  // pinned staging buffer
+  void* dev = nullptr;   // device copy read by the kernels
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+
+#define HIP_TRY(call, what)                                                               \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return nhp::set_error(NHP_EHIP, "%s: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct nhp_batch {
+  hipStream_t stream = nullptr;
+  uint32_t capacity = 0;
+  Slot slot[kSlots];
+  int next = 0;
+};
+
+namespace {
+
+// A slot whose previous launches have finished, with room for `bytes`.
+int take_slot(nhp_batch* b, size_t bytes, Slot** out) {
+  Slot& s = b->slot[b->next];
+  b->next = (b->next + 1) % kSlots;
+  if (s.pending) {
+    HIP_TRY(hipEventSynchronize(s.done), "hipEventSynchronize");
+    s.pending = false;
+  }
+  if (s.bytes < bytes) {
+    size_t nb = std::max(bytes, (size_t)65536);
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.dev) (void)hipFree(s.dev);
+    s.host = s.dev = nullptr;
+    s.bytes = 0;
+    HIP_TRY(hipHostMalloc(&s.host, nb, hipHostMallocDefault), "hipHostMalloc");
+    HIP_TRY(hipMalloc(&s.dev, nb), "hipMalloc");
+    s.bytes = nb;
+  }
+  *out = &s;
+  return NHP_OK;
+}
+
+int finish_slot(nhp_batch* b, Slot* s) {
+  HIP_TRY(hipEventRecord(s->done, b->stream), "hipEventRecord");
+  s->pending = true;
+  return NHP_OK;
+}
+
+int check_plans(nhp_batch* b, nhp_plan* const* plans, uint32_t n) {
+  if (!b) return nhp::set_error(NHP_EINVAL, "batch is NULL");
+  if (n > b->capacity) return nhp::set_error(NHP_EINVAL, "%u plans exceed the batch capacity %u", n, b->capacity);
+  if (n && !plans) return nhp::set_error(NHP_EINVAL, "plans is NULL");
+  for (uint32_t k = 0; k < n; k++) {
+    if (!plans[k]) return nhp::set_error(NHP_EINVAL, "plans[%u] is NULL", k);
+    for (uint32_t m = 0; m < k; m++)
+      if (plans[m] == plans[k]) return nhp::set_error(NHP_EINVAL, "plan listed twice (%u and %u)", m, k);
+  }
+  return NHP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int batch_create(uint32_t capacity, void* stream, nhp_batch** out) {
+  if (!out) return nhp::set_error(NHP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (capacity == 0 || capacity > 65536) return nhp::set_error(NHP_EINVAL, "capacity must be 1..65536");
+  nhp_batch* b = new (std::nothrow) nhp_batch();
+  if (!b) return nhp::set_error(NHP_ENOMEM, "out of host memory");
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  b->capacity = capacity;
+  for (Slot& s : b->slot) {
+    if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+      batch_destroy(b);
+      return nhp::set_error(NHP_EHIP, "hipEventCreate failed");
+    }
+  }
+  *out = b;
+  return nhp::clear_error();
+}
+
+int batch_destroy(nhp_batch* b) {
+  if (!b) return nhp::clear_error();
+  (void)hipStreamSynchronize(b->stream);
+  for (Slot& s : b->slot) {
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.dev) (void)hipFree(s.dev);
+    if (s.done) (void)hipEventDestroy(s.done);
+  }
+  delete b;
+  return nhp::clear_error();
+}
+
+int batch_render(nhp_batch* b, nhp_plan* const* plans, const uint8_t* const* d_images, const int32_t* boxes_frs,
+                 uint32_t n) {
+  int rc = check_plans(b, plans, n);
+  if (rc) return rc;
+  if (n == 0) return nhp::clear_error();
+  if (!d_images || !boxes_frs) return nhp::set_error(NHP_EINVAL, "images or boxes is NULL");
+  std::vector<nhp::RenderJob> jobs(n);
+  int total = 0;
+  for (uint32_t k = 0; k < n; k++) {
+    nhp_plan* p = plans[k];
+    if (!d_images[k]) return nhp::set_error(NHP_EINVAL, "images[%u] is NULL", k);
+    rc = nhp::upload_taps(p, boxes_frs[3 * k], boxes_frs[3 * k + 1], boxes_frs[3 * k + 2]);
+    if (rc) return rc;
+    nhp::RenderJob& r = jobs[k];
+    r.image = d_images[k];
+    r.side = reinterpret_cast<uint8_t*>(p->d.V);
+    r.B = p->d.B;
+    r.taps = p->d.taps;
+    r.N = p->d.nx;
+    r.nt = p->d.nt;
+    r.n_side = 2 * boxes_frs[3 * k + 2] + 1;
+    r.n_len = boxes_frs[3 * k] + boxes_frs[3 * k + 1] + 1;
+    r.blocks = ((r.N + 255) / 256) * r.N * r.nt;
+    r.first_block = total;
+    total += r.blocks;
+  }
+  Slot* s;
+  rc = take_slot(b, jobs.size() * sizeof(nhp::RenderJob), &s);
+  if (rc) return rc;
+  memcpy(s->host, jobs.data(), jobs.size() * sizeof(nhp::RenderJob));
+  HIP_TRY(hipMemcpyAsync(s->dev, s->host, jobs.size() * sizeof(nhp::RenderJob), hipMemcpyHostToDevice, b->stream),
+          "job upload");
+  HIP_TRY(nhp::launch_render_batch(reinterpret_cast<const nhp::RenderJob*>(s->dev), (int)n, total, b->stream),
+          "render launch");
+  for (uint32_t k = 0; k < n; k++) {
+    plans[k]->has_cspace = true;
+    plans[k]->has_value = false;
+  }
+  rc = finish_slot(b, s);
+  return rc ? rc : nhp::clear_error();
+}
+
+int batch_init(nhp_batch* b, nhp_plan* const* plans, const uint32_t* starts_ijt, uint32_t n) {
+  int rc = check_plans(b, plans, n);
+  if (rc) return rc;
+  if (n == 0) return nhp::clear_error();
+  if (!starts_ijt) return nhp::set_error(NHP_EINVAL, "starts is NULL");
+  std::vector<nhp::InitJob> jobs(n);
+  size_t max_n4 = 0;
+  std::vector<uint8_t> codes(n, 0);
+  for (uint32_t k = 0; k < n; k++) {
+    nhp_plan* p = plans[k];
+    if (!p->has_cspace) return nhp::set_error(NHP_ESTATE, "plans[%u] has no obstacle volume", k);
+    const uint32_t si = starts_ijt[3 * k], sj = starts_ijt[3 * k + 1], st = starts_ijt[3 * k + 2];
+    if (si >= p->p.nx || sj >= p->p.nx || st >= p->p.ntheta)
+      return nhp::set_error(NHP_EINVAL, "start of plans[%u] outside its grid", k);
+    const size_t idx = ((size_t)st * p->p.nx + sj) * p->p.nx + si;
+    HIP_TRY(hipMemcpyAsync(&codes[k], p->d.B + idx, 1, hipMemcpyDeviceToHost, b->stream), "start check");
+    jobs[k].V = p->d.V;
+    jobs[k].n4 = (size_t)p->p.nx * p->p.nx * p->p.ntheta / 4;
+    jobs[k].start = (uint32_t)idx;
+    max_n4 = std::max(max_n4, jobs[k].n4);
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream), "start check");
+  for (uint32_t k = 0; k < n; k++)
+    if (codes[k] == NHP_HARD) return nhp::set_error(NHP_ESTART, "start of plans[%u] is in collision", k);
+  Slot* s;
+  rc = take_slot(b, jobs.size() * sizeof(nhp::InitJob), &s);
+  if (rc) return rc;
+  memcpy(s->host, jobs.data(), jobs.size() * sizeof(nhp::InitJob));
+  HIP_TRY(hipMemcpyAsync(s->dev, s->host, jobs.size() * sizeof(nhp::InitJob), hipMemcpyHostToDevice, b->stream),
+          "job upload");
+  HIP_TRY(nhp::launch_init_batch(reinterpret_cast<const nhp::InitJob*>(s->dev), (int)n, max_n4, b->stream),
+          "init launch");
+  for (uint32_t k = 0; k < n; k++) {
+    plans[k]->has_value = true;
+    plans[k]->start[0] = starts_ijt[3 * k];
+    plans[k]->start[1] = starts_ijt[3 * k + 1];
+    plans[k]->start[2] = starts_ijt[3 * k + 2];
+  }
+  rc = finish_slot(b, s);
+  return rc ? rc : nhp::clear_error();
+}
+
+int batch_step(nhp_batch* b, nhp_plan* const* plans, const uint32_t* steps, uint32_t n) {
+  int rc = check_plans(b, plans, n);
+  if (rc) return rc;
+  if (n == 0) return nhp::clear_error();
+  if (!steps) return nhp::set_error(NHP_EINVAL, "steps is NULL");
+  // group the row jobs by section size (one launch each) and collect the x-major jobs
+  static const int kP[4] = {8, 16, 32, 64};
+  std::vector<nhp::SweepJob> group[5];
+  for (uint32_t k = 0; k < n; k++) {
+    nhp_plan* p = plans[k];
+    if (!p->has_value) return nhp::set_error(NHP_ESTATE, "plans[%u] has no value volume (batch_init first)", k);
+    const int mu = p->p.schedule[steps[k] % p->p.n_schedule];
+    nhp::SweepJob row{}, xm{};
+    nhp::make_sweep_jobs(p->d, mu, &row, &xm);
+    if (row.blocks) {
+      int g = 0;
+      while (g < 4 && kP[g] != row.P) g++;
+      if (g == 4) return nhp::set_error(NHP_EINVAL, "plans[%u]: no section size for its curve length", k);
+      group[g].push_back(row);
+    }
+    if (xm.blocks) group[4].push_back(xm);
+  }
+  size_t total_jobs = 0;
+  for (auto& g : group) total_jobs += g.size();
+  Slot* s;
+  rc = take_slot(b, total_jobs * sizeof(nhp::SweepJob), &s);
+  if (rc) return rc;
+  nhp::SweepJob* h = reinterpret_cast<nhp::SweepJob*>(s->host);
+  size_t off = 0;
+  int blocks[5] = {0, 0, 0, 0, 0};
+  size_t first[5];
+  for (int g = 0; g < 5; g++) {
+    first[g] = off;
+    for (nhp::SweepJob& j : group[g]) {
+      j.first_block = blocks[g];
+      blocks[g] += j.blocks;
+      h[off++] = j;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(s->dev, s->host, total_jobs * sizeof(nhp::SweepJob), hipMemcpyHostToDevice, b->stream),
+          "job upload");
+  const nhp::SweepJob* d = reinterpret_cast<const nhp::SweepJob*>(s->dev);
+  for (int g = 0; g < 5; g++) {
+    if (group[g].empty()) continue;
+    HIP_TRY(nhp::launch_sweep_batch(d + first[g], (int)group[g].size(), blocks[g], g < 4 ? kP[g] : 0, g == 4,
+                                    b->stream),
+            "sweep launch");
+  }
+  rc = finish_slot(b, s);
+  return rc ? rc : nhp::clear_error();
+}
+
+int batch_sweep(nhp_batch* b, nhp_plan* const* plans, const uint32_t* starts_ijt, const uint32_t* n_cycles,
+                uint32_t n) {
+  int rc = check_plans(b, plans, n);
+  if (rc) return rc;
+  if (n == 0) return nhp::clear_error();
+  if (!n_cycles) return nhp::set_error(NHP_EINVAL, "n_cycles is NULL");
+  rc = batch_init(b, plans, starts_ijt, n);
+  if (rc) return rc;
+  uint32_t max_steps = 0;
+  std::vector<uint32_t> total(n);
+  for (uint32_t k = 0; k < n; k++) {
+    total[k] = n_cycles[k] * plans[k]->p.n_schedule;
+    max_steps = std::max(max_steps, total[k]);
+  }
+  std::vector<nhp_plan*> live;
+  std::vector<uint32_t> step;
+  live.reserve(n);
+  step.reserve(n);
+  for (uint32_t s = 0; s < max_steps; s++) {
+    live.clear();
+    step.clear();
+    for (uint32_t k = 0; k < n; k++)
+      if (s < total[k]) {
+        live.push_back(plans[k]);
+        step.push_back(s);
+      }
+    rc = batch_step(b, live.data(), step.data(), (uint32_t)live.size());
+    if (rc) return rc;
+  }
+  return nhp::clear_error();
+}
+
+int batch_extract(nhp_batch* b, nhp_plan* const* plans, uint32_t n, const uint32_t* goals_ijt, const uint32_t* radius,
+                  const uint32_t* w_xy_q10, const uint32_t* w_t_q10, nhp_step* h_steps, uint32_t cap_per_plan,
+                  uint32_t* n_steps, int32_t* status, uint32_t* best_ijt, uint32_t* goal_value_q10,
+                  uint32_t* score_q10) {
+  int rc = check_plans(b, plans, n);
+  if (rc) return rc;
+  if (n == 0) return nhp::clear_error();
+  if (!goals_ijt || !radius || !w_xy_q10 || !w_t_q10 || !n_steps || !status)
+    return nhp::set_error(NHP_EINVAL, "a required array is NULL");
+  if (cap_per_plan > 0 && !h_steps) return nhp::set_error(NHP_EINVAL, "h_steps is NULL");
+  std::vector<nhp::ExArgs> args(n);
+  for (uint32_t k = 0; k < n; k++) {
+    nhp_plan* p = plans[k];
+    if (!p->has_value) return nhp::set_error(NHP_ESTATE, "plans[%u]: extract before any sweep", k);
+    const uint32_t gi = goals_ijt[3 * k], gj = goals_ijt[3 * k + 1], gt = goals_ijt[3 * k + 2];
+    if (gi >= p->p.nx || gj >= p->p.nx || gt >= p->p.ntheta)
+      return nhp::set_error(NHP_EINVAL, "goal of plans[%u] outside its grid", k);
+    if (radius[k] > (uint32_t)nhp::kMaxRadius) return nhp::set_error(NHP_EINVAL, "goal radius of plans[%u] > 31", k);
+    args[k] = nhp::ExArgs{p->d, p->start[0], p->start[1], p->start[2], gi, gj, gt, (int)radius[k], w_xy_q10[k],
+                          w_t_q10[k]};
+  }
+  Slot* s;
+  const size_t head_words = (size_t)n * nhp::kExHeader;
+  rc = take_slot(b, std::max(args.size() * sizeof(nhp::ExArgs), head_words * 4), &s);
+  if (rc) return rc;
+  memcpy(s->host, args.data(), args.size() * sizeof(nhp::ExArgs));
+  HIP_TRY(hipMemcpyAsync(s->dev, s->host, args.size() * sizeof(nhp::ExArgs), hipMemcpyHostToDevice, b->stream),
+          "job upload");
+  HIP_TRY(nhp::launch_extract_batch(reinterpret_cast<const nhp::ExArgs*>(s->dev), (int)n, b->stream),
+          "extract launch");
+  // the pinned staging buffer now receives the result headers (the upload
+  // ahead of them on the stream has been consumed by then)
+  uint32_t* head = reinterpret_cast<uint32_t*>(s->host);
+  for (uint32_t k = 0; k < n; k++)
+    HIP_TRY(hipMemcpyAsync(head + (size_t)k * nhp::kExHeader, plans[k]->d.extract, nhp::kExHeader * 4,
+                           hipMemcpyDeviceToHost, b->stream),
+            "result copy");
+  HIP_TRY(hipStreamSynchronize(b->stream), "result copy");
+  std::vector<uint32_t> heads(head, head + head_words);
+  std::vector<uint32_t> raw;
+  for (uint32_t k = 0; k < n; k++) {
+    const uint32_t* h = &heads[(size_t)k * nhp::kExHeader];
+    n_steps[k] = h[1];
+    if (h[0] != 0) {
+      status[k] = NHP_EUNREACH;
+      continue;
+    }
+    if (best_ijt) memcpy(best_ijt + 3 * k, h + 2, 3 * sizeof(uint32_t));
+    if (goal_value_q10) goal_value_q10[k] = h[5];
+    if (score_q10) score_q10[k] = h[6];
+    const uint32_t m = h[1];
+    if (m > NHP_MAX_STEPS_DEVICE || m > cap_per_plan) {
+      status[k] = NHP_ECAP;
+      continue;
+    }
+    raw.resize((size_t)m * nhp::kExStepWords);
+    if (m) {
+      HIP_TRY(hipMemcpyAsync(raw.data(), plans[k]->d.extract + nhp::kExHeader, raw.size() * 4,
+                             hipMemcpyDeviceToHost, b->stream),
+              "result copy");
+      HIP_TRY(hipStreamSynchronize(b->stream), "result copy");
+    }
+    nhp_step* out = h_steps + (size_t)k * cap_per_plan;
+    for (uint32_t q = 0; q < m; q++) {  // device order is goal -> start
+      const uint32_t* w = &raw[(size_t)(m - 1 - q) * nhp::kExStepWords];
+      nhp_step& o = out[q];
+      memset(&o, 0, sizeof(o));
+      o.maneuver = (uint8_t)w[0];
+      o.steps = w[1];
+      memcpy(o.from_ijt, w + 2, 3 * sizeof(uint32_t));
+      memcpy(o.to_ijt, w + 5, 3 * sizeof(uint32_t));
+      o.cost_q10 = w[8];
+    }
+    status[k] = NHP_OK;
+  }
+  rc = finish_slot(b, s);
+  return rc ? rc : nhp::clear_error();
+}
+
+}  // extern "C"

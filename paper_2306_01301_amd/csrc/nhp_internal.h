@@ -56,6 +56,39 @@ struct DevPlan {
   int n_schedule;
 };
 
+// One maneuver of one plan, as the sweep kernels see it.  Row jobs cover
+// turn curves (cyclic) or the y-major straight planes; x-major jobs cover
+// the x-major straight planes.  Plain pointers and integers only, so job
+// tables can be copied to the device for batched launches.
+struct SweepJob {
+  uint32_t* V;
+  const uint8_t* B;
+  const int32_t* offx;      // turns: offsets of this maneuver's curves (reduced mod N)
+  const int32_t* offy;
+  const int16_t* skew;      // straights: B(y', T)
+  const int32_t* planes;    // straights: heading planes of this job's family
+  const uint32_t* edge_len; // straights: this maneuver's edge lengths per plane
+  const int32_t* fwd;       // straights: forward signs
+  int N, L;                 // grid side, curve length
+  int cyclic, dir, mu_forward;
+  int tiles_x, blocks, first_block;
+  int P;                    // steps per wave (row jobs)
+  uint32_t ct, lq;          // transition cost; turn edge length
+};
+
+struct InitJob {
+  uint32_t* V;
+  size_t n4;       // poses / 4
+  uint32_t start;  // start pose index
+  uint32_t pad;
+};
+
+int pick_section(int len);
+int make_sweep_jobs(const DevPlan& d, int mu, SweepJob* row, SweepJob* xmaj);
+hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool xmajor,
+                              hipStream_t s);
+hipError_t launch_init_batch(const InitJob* d_jobs, int n_jobs, size_t max_n4, hipStream_t s);
+
 // extract buffer layout (uint32 words)
 constexpr int kExHeader = 16;  // status, n_steps, best i, j, T, V(best), score, ...
 constexpr int kExStepWords = 9;
@@ -67,4 +100,50 @@ hipError_t launch_render(const DevPlan& d, const uint8_t* image, int n_side, int
 hipError_t launch_extract(const DevPlan& d, uint32_t si, uint32_t sj, uint32_t st, uint32_t gi, uint32_t gj,
                           uint32_t gt, int radius, uint32_t w_xy, uint32_t w_t, hipStream_t s);
 
+// Goal search and back-tracking arguments of one plan.
+struct ExArgs {
+  DevPlan d;
+  uint32_t si, sj, st, gi, gj, gt;
+  int radius;
+  uint32_t w_xy, w_t;
+};
+hipError_t launch_extract_batch(const ExArgs* d_args, int n, hipStream_t s);
+
+// Rendering of one plan: sideways pass from the image into `side`, then the
+// lengthwise pass into B.  Batched launches list several plans.
+struct RenderJob {
+  const uint8_t* image;
+  uint8_t* side;
+  uint8_t* B;
+  const int32_t* taps;
+  int N, nt, n_side, n_len;
+  int blocks, first_block;
+};
+hipError_t launch_render_batch(const RenderJob* d_jobs, int n_jobs, int total_blocks, hipStream_t s);
+
+}  // namespace nhp
+
+// The plan object behind the opaque handle of the C ABI.
+struct nhp_plan {
+  nhp_params p{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  nhp::HostTables t;
+  nhp::DevPlan d{};
+  bool has_cspace = false;
+  bool has_value = false;
+  uint32_t start[3] = {0, 0, 0};
+  int front = -1, rear = -1, half_width = -1;  // box of the last render (sample offsets cached)
+  hipGraphExec_t cycle = nullptr;  // one cycle of the schedule, captured once, replayed per cycle
+  bool graph_failed = false;       // capture unavailable: launch the kernels directly
+};
+
+namespace nhp {
+// Thread-local error text of the C ABI (nhp_api.cpp).
+int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int clear_error();
+int upload_taps(nhp_plan* plan, int front, int rear, int half_width);
 }  // namespace nhp

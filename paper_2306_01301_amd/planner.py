@@ -73,6 +73,14 @@ SIGNATURES = {
     "plan_device_ptrs": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "plan_get_tables": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "plan_last_error": (ctypes.c_char_p, []),
+    "batch_create": (ctypes.c_int, [_u32, _vp, ctypes.POINTER(_vp)]),
+    "batch_destroy": (ctypes.c_int, [_vp]),
+    "batch_render": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
+    "batch_init": (ctypes.c_int, [_vp, _vp, _vp, _u32]),
+    "batch_step": (ctypes.c_int, [_vp, _vp, _vp, _u32]),
+    "batch_sweep": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
+    "batch_extract": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp, ctypes.POINTER(NhpStep), _u32, _vp, _vp,
+                                     _vp, _vp, _vp]),
 }
 
 _lib = None
@@ -263,3 +271,83 @@ def plan_scene(scene, radius: Optional[int] = None, device=None) -> Tuple[Planne
     p.sweep(scene.start, scene.n_cycles)
     path = p.extract(scene.goal, scene.goal_radius if radius is None else radius, scene.w_xy, scene.w_t)
     return p, path
+
+
+def _u32array(values) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(values, dtype=np.uint32).reshape(-1))
+
+
+class Batch:
+    """Batched launches over many plans (include/nhp.h, batch_*): one launch
+    per pass covers the current work of every listed plan."""
+
+    def __init__(self, capacity: int, stream: Optional[torch.cuda.Stream] = None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._b = ctypes.c_void_p()
+        _check(lib().batch_create(int(capacity), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._b)),
+               "batch_create")
+        self.capacity = int(capacity)
+
+    @staticmethod
+    def _handles(planners):
+        arr = (ctypes.c_void_p * max(1, len(planners)))()
+        for k, p in enumerate(planners):
+            arr[k] = p._plan.value
+        return arr
+
+    def render(self, planners, images, vehicles) -> None:
+        imgs = [im.contiguous() for im in images]
+        self._keep = imgs
+        ptrs = (ctypes.c_void_p * max(1, len(imgs)))(*[im.data_ptr() for im in imgs])
+        boxes = np.ascontiguousarray(np.asarray(vehicles, dtype=np.int32).reshape(-1))
+        _check(lib().batch_render(self._b, self._handles(planners), ptrs, boxes.ctypes.data, len(planners)),
+               "batch_render")
+
+    def init(self, planners, starts) -> None:
+        s = _u32array(starts)
+        _check(lib().batch_init(self._b, self._handles(planners), s.ctypes.data, len(planners)), "batch_init")
+
+    def step(self, planners, steps) -> None:
+        s = _u32array(steps)
+        _check(lib().batch_step(self._b, self._handles(planners), s.ctypes.data, len(planners)), "batch_step")
+
+    def sweep(self, planners, starts, n_cycles) -> None:
+        s, n = _u32array(starts), _u32array(n_cycles)
+        _check(lib().batch_sweep(self._b, self._handles(planners), s.ctypes.data, n.ctypes.data, len(planners)),
+               "batch_sweep")
+
+    def extract(self, planners, goals, radius, w_xy, w_t, cap: int = 512):
+        """Returns a list with a Path or an NhpError status code per plan."""
+        n = len(planners)
+        g, r, wx, wt = _u32array(goals), _u32array(radius), _u32array(w_xy), _u32array(w_t)
+        steps = (NhpStep * max(1, n * cap))()
+        n_steps = np.zeros(n, np.uint32)
+        status = np.zeros(n, np.int32)
+        best = np.zeros(3 * n, np.uint32)
+        val = np.zeros(n, np.uint32)
+        score = np.zeros(n, np.uint32)
+        _check(lib().batch_extract(self._b, self._handles(planners), n, g.ctypes.data, r.ctypes.data,
+                                   wx.ctypes.data, wt.ctypes.data, steps, int(cap), n_steps.ctypes.data,
+                                   status.ctypes.data, best.ctypes.data, val.ctypes.data, score.ctypes.data),
+               "batch_extract")
+        out = []
+        for k in range(n):
+            if status[k] != 0:
+                out.append(int(status[k]))
+                continue
+            ss = steps[k * cap:k * cap + int(n_steps[k])]
+            out.append(Path([Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_ijt),
+                                  tuple(int(v) for v in s.to_ijt), int(s.cost_q10)) for s in ss],
+                            tuple(int(v) for v in best[3 * k:3 * k + 3]), int(val[k]), int(score[k])))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_b", None) is not None and self._b.value:
+            lib().batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

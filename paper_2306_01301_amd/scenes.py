@@ -122,17 +122,24 @@ def mixed_clutter(rng, n: int, occupancy: float) -> np.ndarray:
     """Rectangles (sides 2..16) and disks (radius 2..10) until the hard
     fraction reaches `occupancy`."""
     img = np.zeros((n, n), np.uint8)
-    yy, xx = np.mgrid[0:n, 0:n]
     target = occupancy * n * n
-    while np.count_nonzero(img) < target:
+    filled = 0
+    while filled < target:
         if rng.random() < 0.5:
             w, h = int(rng.integers(2, 17)), int(rng.integers(2, 17))
             x, y = int(rng.integers(0, n - w + 1)), int(rng.integers(0, n - h + 1))
-            img[y:y + h, x:x + w] = HARD
+            patch = img[y:y + h, x:x + w]
+            filled += int(np.count_nonzero(patch != HARD))
+            patch[:] = HARD
         else:
             rad = int(rng.integers(2, 11))
             cx, cy = int(rng.integers(0, n)), int(rng.integers(0, n))
-            img[(xx - cx) ** 2 + (yy - cy) ** 2 <= rad * rad] = HARD
+            y0, y1, x0, x1 = max(0, cy - rad), min(n, cy + rad + 1), max(0, cx - rad), min(n, cx + rad + 1)
+            yy, xx = np.mgrid[y0:y1, x0:x1]
+            disk = (xx - cx) ** 2 + (yy - cy) ** 2 <= rad * rad
+            patch = img[y0:y1, x0:x1]
+            filled += int(np.count_nonzero(disk & (patch != HARD)))
+            patch[disk] = HARD
     return img
 
 

@@ -241,3 +241,23 @@ def test_maze_512_full_size():
         assert isinstance(path, P.NhpError) and path.rc == rc
     else:
         _check_path(path, goal, steps, V)
+
+
+def test_graph_replays_match_eager_launches():
+    """sweep_n_turns replays a captured cycle graph; every replay, with eager
+    work and synchronisations between replays, matches cycles launched one
+    kernel at a time through sweep_one."""
+    sc = scenes.random_small(31, n=96, nt=48, R=6.0, n_cycles=3)
+    p = _planner(sc)
+    p.render(_dev(sc.image), sc.vehicle)
+    for rep in range(4):
+        p.sweep(sc.start, rep + 1)          # graph replays
+        graph = p.value_numpy()
+        p.sweep(sc.start, 0)                # eager: init only, then one kernel per sweep
+        for _ in range(rep + 1):
+            for mu in sc.schedule:
+                p.sweep_one(mu)
+        eager = p.value_numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(graph, eager), rep
+    p.close()
