@@ -99,7 +99,15 @@ def batch_comparison() -> dict:
     serving.run_batched(reqs[:8])  # warm-up
     serving.run_single(reqs[:8])
     out = {"workload": "batch_64", "plans": len(reqs), "pose_updates": updates}
-    for name, fn in (("one_plan_per_launch", serving.run_single), ("batched", serving.run_batched)):
+
+    def continuous(rs):
+        srv = serving.Server(1 << 60, max_live=len(rs))
+        res = srv.run(rs, [0.0] * len(rs))
+        srv.close()
+        return res
+
+    for name, fn in (("one_plan_per_launch", serving.run_single), ("batched", serving.run_batched),
+                     ("continuous", continuous)):
         res = fn(reqs)
         s = serving.latency_summary(res)
         s["pose_updates_per_s"] = updates / max(r.finished for r in res)

@@ -222,6 +222,14 @@ int batch_extract(nhp_batch* batch, nhp_plan* const* plans, uint32_t n, const ui
                   nhp_step* h_steps, uint32_t cap_per_plan, uint32_t* n_steps, int32_t* status,
                   uint32_t* best_ijt, uint32_t* goal_value_q10, uint32_t* score_q10);
 
+/* Tuning: the number of steps each wave of a sweep workgroup holds for
+ * curves of length `curve_len` (ntheta for turns, nx for straights): 8, 16,
+ * 32 or 64 with ceil(curve_len / steps) <= 16; 0 restores the built-in
+ * choice.  Process-wide; plans that already captured their cycle graph keep
+ * the choice they captured.  Every valid choice gives identical results and
+ * only changes speed (the autotuner measures them).  Errors: NHP_EINVAL. */
+int nhp_set_section_steps(uint32_t curve_len, uint32_t steps);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* plan_last_error(void);
 

@@ -20,24 +20,24 @@ __device__ __forceinline__ int wrapn(int v, int N) { return v - ((v >= N) ? N : 
 __device__ __forceinline__ int tap_dx(int32_t p) { return (int)(p & 0xffff); }
 __device__ __forceinline__ int tap_dy(int32_t p) { return (int)((uint32_t)p >> 16); }
 
-// Samples of a pass are read 4 at a time with independent loads (the tap
+// Samples of a pass are read 8 at a time with independent loads (the tap
 // count is a run-time value, so a plain loop would serialise them).
 template <bool WALLED>
 __device__ __forceinline__ uint32_t max_over(const uint8_t* __restrict__ src, const int32_t* __restrict__ tp, int n,
                                              int i, int j, int N) {
   uint32_t m = 0;
   int g = 0;
-  for (; g + 4 <= n; g += 4) {
-    uint32_t q[4];
+  for (; g + 8 <= n; g += 8) {
+    uint32_t q[8];
 #pragma unroll
-    for (int e = 0; e < 4; e++) {
+    for (int e = 0; e < 8; e++) {
       const int32_t t = tp[g + e];
       const int y = wrapn(j + tap_dy(t), N), x = wrapn(i + tap_dx(t), N);
       q[e] = src[(size_t)y * N + x];
       if (WALLED) q[e] = (y == 0 || x == 0) ? kHard : q[e];
     }
 #pragma unroll
-    for (int e = 0; e < 4; e++) m = q[e] > m ? q[e] : m;
+    for (int e = 0; e < 8; e++) m = q[e] > m ? q[e] : m;
   }
   for (; g < n; g++) {
     const int32_t t = tp[g];
@@ -70,38 +70,53 @@ __device__ __forceinline__ int find_render_job(const RenderJob* __restrict__ job
   return lo;
 }
 
+// The block's plane's sample offsets are staged in LDS once per block.
+__device__ __forceinline__ void stage_taps(const int32_t* __restrict__ src, int n, int32_t* sh) {
+  for (int g = threadIdx.x; g < n; g += blockDim.x) sh[g] = src[g];
+  __syncthreads();
+}
+
 // side[T][j][i] = max over sideways samples of the walled image
-__device__ __forceinline__ void side_pose(const RenderJob& r, int b) {
+__device__ __forceinline__ void side_pose(const RenderJob& r, int b, int32_t* sh) {
   int T, j, i;
   render_pose(r, b, T, j, i);
+  stage_taps(r.taps + (size_t)T * 2 * kMaxTaps, r.n_side, sh);
   if (i >= r.N) return;
-  const uint32_t m = max_over<true>(r.image, r.taps + (size_t)T * 2 * kMaxTaps, r.n_side, i, j, r.N);
+  const uint32_t m = max_over<true>(r.image, sh, r.n_side, i, j, r.N);
   r.side[((size_t)T * r.N + j) * r.N + i] = (uint8_t)m;
 }
 
 // B[T][j][i] = max over lengthwise samples of side[T]; walls forced hard
-__device__ __forceinline__ void len_pose(const RenderJob& r, int b) {
+__device__ __forceinline__ void len_pose(const RenderJob& r, int b, int32_t* sh) {
   int T, j, i;
   render_pose(r, b, T, j, i);
+  stage_taps(r.taps + (size_t)T * 2 * kMaxTaps + kMaxTaps, r.n_len, sh);
   if (i >= r.N) return;
   const size_t NN = (size_t)r.N * r.N;
-  uint32_t m = max_over<false>(r.side + (size_t)T * NN, r.taps + (size_t)T * 2 * kMaxTaps + kMaxTaps, r.n_len, i, j,
-                               r.N);
+  uint32_t m = max_over<false>(r.side + (size_t)T * NN, sh, r.n_len, i, j, r.N);
   if (i == 0 || j == 0) m = kHard;
   r.B[(size_t)T * NN + (size_t)j * r.N + i] = (uint8_t)m;
 }
 
-__global__ __launch_bounds__(256) void render_side_kernel(RenderJob r) { side_pose(r, blockIdx.x); }
-__global__ __launch_bounds__(256) void render_len_kernel(RenderJob r) { len_pose(r, blockIdx.x); }
+__global__ __launch_bounds__(256) void render_side_kernel(RenderJob r) {
+  __shared__ int32_t sh[kMaxTaps];
+  side_pose(r, blockIdx.x, sh);
+}
+__global__ __launch_bounds__(256) void render_len_kernel(RenderJob r) {
+  __shared__ int32_t sh[kMaxTaps];
+  len_pose(r, blockIdx.x, sh);
+}
 
 __global__ __launch_bounds__(256) void render_side_batch_kernel(const RenderJob* __restrict__ jobs, int n_jobs) {
+  __shared__ int32_t sh[kMaxTaps];
   const int k = find_render_job(jobs, n_jobs, blockIdx.x);
-  side_pose(jobs[k], blockIdx.x - jobs[k].first_block);
+  side_pose(jobs[k], blockIdx.x - jobs[k].first_block, sh);
 }
 
 __global__ __launch_bounds__(256) void render_len_batch_kernel(const RenderJob* __restrict__ jobs, int n_jobs) {
+  __shared__ int32_t sh[kMaxTaps];
   const int k = find_render_job(jobs, n_jobs, blockIdx.x);
-  len_pose(jobs[k], blockIdx.x - jobs[k].first_block);
+  len_pose(jobs[k], blockIdx.x - jobs[k].first_block, sh);
 }
 
 }  // namespace

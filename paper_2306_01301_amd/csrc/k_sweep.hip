@@ -29,6 +29,8 @@
 // x-major straight family (|tan| <= 1) puts the lanes on a column instead;
 // those planes are loaded and stored row-wise into an LDS tile per wave and
 // transposed there.
+#include <atomic>
+
 #include "nhp_internal.h"
 
 namespace nhp {
@@ -430,12 +432,29 @@ constexpr int XQ = 32;  // columns per x-major chunk
 
 }  // namespace
 
-// Steps per wave: the smallest power of two in [8, 64] that splits the curve
-// into at most 16 sections (16 waves of a 1024-thread workgroup).
+// Steps per wave chosen for a curve length (0 = not set), process-wide.
+static std::atomic<uint8_t> g_section_steps[1025];
+
+bool valid_section(int len, int P) { return (P == 8 || P == 16 || P == 32 || P == 64) && (len + P - 1) / P <= 16; }
+
+// Steps per wave: the tuned choice for this curve length, else the smallest
+// power of two in [8, 64] that splits the curve into at most 16 sections
+// (16 waves of a 1024-thread workgroup).
 int pick_section(int len) {
+  if (len >= 1 && len <= 1024) {
+    const int t = g_section_steps[len].load(std::memory_order_relaxed);
+    if (t && valid_section(len, t)) return t;
+  }
   int P = 8;
   while (P < 64 && P * 16 < len) P <<= 1;
   return (P * 16 >= len) ? P : 0;
+}
+
+int set_section_steps(int len, int P) {
+  if (len < 1 || len > 1024) return NHP_EINVAL;
+  if (P != 0 && !valid_section(len, P)) return NHP_EINVAL;
+  g_section_steps[len].store((uint8_t)P, std::memory_order_relaxed);
+  return NHP_OK;
 }
 
 // The jobs of one maneuver of one plan: a row job (turns, or the y-major

@@ -115,6 +115,12 @@ extern "C" {
 
 const char* plan_last_error(void) { return g_err; }
 
+int nhp_set_section_steps(uint32_t curve_len, uint32_t steps) {
+  if (nhp::set_section_steps((int)curve_len, (int)steps) != NHP_OK)
+    return fail(NHP_EINVAL, "steps %u is not valid for curves of length %u", steps, curve_len);
+  return ok();
+}
+
 size_t plan_workspace_bytes(const nhp_params* params) {
   if (check_params(params) != NHP_OK) return 0;
   return layout_of(*params).total;

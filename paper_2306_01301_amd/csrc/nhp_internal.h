@@ -84,6 +84,7 @@ struct InitJob {
 };
 
 int pick_section(int len);
+int set_section_steps(int len, int P);
 int make_sweep_jobs(const DevPlan& d, int mu, SweepJob* row, SweepJob* xmaj);
 hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool xmajor,
                               hipStream_t s);

@@ -73,6 +73,7 @@ SIGNATURES = {
     "plan_device_ptrs": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "plan_get_tables": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "plan_last_error": (ctypes.c_char_p, []),
+    "nhp_set_section_steps": (ctypes.c_int, [_u32, _u32]),
     "batch_create": (ctypes.c_int, [_u32, _vp, ctypes.POINTER(_vp)]),
     "batch_destroy": (ctypes.c_int, [_vp]),
     "batch_render": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
@@ -97,7 +98,29 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.restype, fn.argtypes = res, args
         _lib = L
+        apply_tuning()
     return _lib
+
+
+TUNING_PATH = os.path.join(_HERE, "tuning.json")
+
+
+def apply_tuning(path: str = TUNING_PATH) -> dict:
+    """Hands the measured section sizes (autotune.py) to the library."""
+    import json
+
+    try:
+        with open(path) as f:
+            table = json.load(f).get("section_steps", {})
+    except (OSError, ValueError):
+        return {}
+    for length, steps in table.items():
+        _lib.nhp_set_section_steps(int(length), int(steps))
+    return table
+
+
+def set_section_steps(curve_len: int, steps: int) -> None:
+    _check(lib().nhp_set_section_steps(int(curve_len), int(steps)), "nhp_set_section_steps")
 
 
 class NhpError(RuntimeError):

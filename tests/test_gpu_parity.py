@@ -261,3 +261,35 @@ def test_graph_replays_match_eager_launches():
         torch.cuda.synchronize()
         assert np.array_equal(graph, eager), rep
     p.close()
+
+
+@pytest.mark.parametrize("N,L", [(128, 128), (96, 72)])
+def test_every_section_size_matches_oracle(N, L):
+    """Every section size the tuner may pick gives the oracle's values."""
+    rng = np.random.default_rng(N + L)
+    sc = scenes.random_small(int(rng.integers(1 << 30)), n=N, nt=L, R=6.0, n_rect=N // 8).with_(vehicle=(3, 1, 1))
+    prob = problem_of(sc)
+    B = oracle.render(prob, sc.image, *sc.vehicle)
+    V0 = rng.integers(0, 1 << 22, size=B.shape, dtype=np.uint64).astype(np.uint32)
+    V0[rng.random(B.shape) < 0.4] = INF
+    try:
+        for steps in (8, 16, 32, 64):
+            if (L + steps - 1) // steps > 16 and (N + steps - 1) // steps > 16:
+                continue
+            for length in (N, L):
+                if (length + steps - 1) // steps <= 16:
+                    P.set_section_steps(length, steps)
+            p = _planner(sc)
+            p.set_cspace(_dev(B))
+            for mu in range(6):
+                note("section %d %s mu=%s" % (steps, (N, L), oracle.NAMES[mu]))
+                p.value.copy_(_dev(V0.view(np.int32)))
+                p.sweep_one(mu)
+                want = V0.copy()
+                oracle.sweep(prob, mu, B, want)
+                assert np.array_equal(p.value_numpy(), want), (steps, mu)
+            p.close()
+    finally:
+        P.set_section_steps(N, 0)
+        P.set_section_steps(L, 0)
+        P.apply_tuning()
