@@ -90,8 +90,12 @@ def _L():
         lib.or_goal_search.argtypes = [P(_Problem), vp, vp, i32, i32, i32, i32, u32, u32, vp, vp]
         lib.or_backtrack.argtypes = [P(_Problem), vp, vp, i32, i32, i32, vp, vp, i32, vp]
         lib.or_set_threads.argtypes = [i32]
+        lib.or_reach.argtypes = [P(_Problem), vp, i32, i32, i32, i32, vp]
+        lib.or_reach_goal.argtypes = [P(_Problem), vp, i32, i32, i32, i32, vp, vp]
+        lib.or_reach_backtrack.argtypes = [P(_Problem), vp, vp, vp, vp, i32, vp]
         for name in ("or_tables_export", "or_render_taps", "or_render", "or_init", "or_sweep",
-                     "or_cycles", "or_goal_search", "or_backtrack", "or_set_threads"):
+                     "or_cycles", "or_goal_search", "or_backtrack", "or_set_threads", "or_reach",
+                     "or_reach_goal", "or_reach_backtrack"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -236,3 +240,39 @@ def plan(prob: Problem, image, vehicle, start, goal, n_cycles, d=0, w_xy=0, w_t=
     best, score = goal_search(prob, B, V, goal, d, w_xy, w_t)
     steps = backtrack(prob, B, V, start, best)
     return dict(B=B, V=V, best=best, score=score, steps=steps)
+
+
+# ---------------------------------------------------------------- App. C
+
+UNREACHED = 255
+
+
+def reach(prob: Problem, B: np.ndarray, start, n_cycles: int) -> np.ndarray:
+    """Maneuver-count reachability (hard obstacles only): per vertex the
+    smallest m <= n_cycles with the vertex reachable in m maneuvers, else 255."""
+    assert B.dtype == np.uint8
+    level = np.empty(B.shape, np.uint8)
+    p = prob.c()
+    _check(_L().or_reach(ctypes.byref(p), _ptr(B), *[int(v) for v in start], int(n_cycles), _ptr(level)),
+           "or_reach")
+    return level
+
+
+def reach_goal(prob: Problem, level: np.ndarray, goal, d: int):
+    best = np.zeros(3, np.int32)
+    lv = np.zeros(1, np.int32)
+    p = prob.c()
+    _check(_L().or_reach_goal(ctypes.byref(p), _ptr(level), *[int(v) for v in goal], int(d), _ptr(best), _ptr(lv)),
+           "or_reach_goal")
+    return tuple(int(v) for v in best), int(lv[0])
+
+
+def reach_backtrack(prob: Problem, B, level, best, cap: int = 1024) -> List[Step]:
+    steps = (_Step * max(cap, 1))()
+    n = ctypes.c_int32(0)
+    g = np.array(best, np.int32)
+    p = prob.c()
+    _check(_L().or_reach_backtrack(ctypes.byref(p), _ptr(B), _ptr(level), _ptr(g), ctypes.addressof(steps),
+                                   int(cap), ctypes.addressof(n)), "or_reach_backtrack")
+    return [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_), tuple(int(v) for v in s.to),
+                 int(s.cost)) for s in steps[: n.value]]

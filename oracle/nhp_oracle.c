@@ -22,6 +22,8 @@
  *   cycles     Sec. XVI.A: N cycles of LF, SF, RB, RF, SB, LB.
  *   goal       Sec. IX: best vertex in a window around the goal.
  *   backtrack  Sec. X, eq. (32): reverse Bellman steps back to the start.
+ *   reach      App. C, Insert 2: reachability by maneuver count (hard
+ *              obstacles only), its goal search and back-tracking.
  *
  * Integer reading of the paper's floating-point costs (the paper is silent on
  * a fixed-point form): values are uint32 in 1/1024 cell, 0xFFFFFFFF is
@@ -683,6 +685,230 @@ int or_backtrack(const or_problem* p, const uint8_t* B, const uint32_t* V, int32
   if (rc) return rc;
   if (n > cap) return OR_ECAP;
   for (int32_t a = 0, b = n - 1; a < b; a++, b--) { /* start -> goal order */
+    or_step t = steps[a];
+    steps[a] = steps[b];
+    steps[b] = t;
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* exported: reachability with maneuver counting (App. C)             */
+/* ------------------------------------------------------------------ */
+
+/* App. C replaces the costs by the number of maneuvers: edges inside a
+ * maneuver cost nothing, every transition costs one, and only hard
+ * obstacles remain (any code below OR_HARD counts as free).  A vertex then
+ * needs one bit per maneuver count, "reachable with at most m maneuvers".
+ * The paper stores the bit inverted (0 = reachable) so that its sweep is an
+ * AND with the previous volume followed by an OR with the obstacle bit; here
+ * the same logic is written with 1 = reachable:
+ *   along a curve:  r = (r_carried OR R_m(X)) AND free(X);  out(X) = r
+ * and every maneuver of a cycle starts from the same R_m (the volumes of the
+ * maneuver vertices are separate), after which R_{m+1} is the union of the
+ * maneuvers' outputs.  Turns close their circle (two loops), straights start
+ * at the wall, as in the cost sweeps.  The result is stored as a level per
+ * vertex: the smallest m with the vertex in R_m (255 when none up to n). */
+
+static void reach_turn(const or_problem* p, const or_tables* tb, int mu, const uint8_t* B, const uint8_t* R,
+                       uint8_t* out) {
+  int32_t N = p->nx, L = p->nt;
+  int left = turn_left(mu), asc = turn_ascending(mu);
+#pragma omp parallel
+  {
+    uint8_t* carry = (uint8_t*)malloc((size_t)N);
+#pragma omp for schedule(static)
+    for (int32_t yp = 0; yp < N; yp++) {
+      memset(carry, 0, (size_t)N);
+      for (int32_t t = 0; t < 2 * L; t++) {
+        int32_t T = asc ? (t % L) : (L - 1 - (t % L));
+        int32_t ox, oy;
+        turn_offset(p, tb, left, T, &ox, &oy);
+        int32_t j = wrap((int64_t)yp + oy, N);
+        for (int32_t xp = 0; xp < N; xp++) {
+          size_t x = cell_index(p, wrap((int64_t)xp + ox, N), j, T);
+          uint8_t r = (uint8_t)((carry[xp] | R[x]) & (B[x] != OR_HARD));
+          out[x] |= r;
+          carry[xp] = r;
+        }
+      }
+    }
+    free(carry);
+  }
+}
+
+static void reach_straight(const or_problem* p, const or_tables* tb, int mu, const uint8_t* B, const uint8_t* R,
+                           uint8_t* out) {
+  int32_t N = p->nx, L = p->nt;
+#pragma omp parallel
+  {
+    uint8_t* carry = (uint8_t*)malloc((size_t)N);
+#pragma omp for schedule(static)
+    for (int32_t T = 0; T < L; T++) {
+      int asc = straight_ascending(mu, tb->J[T]);
+      memset(carry, 0, (size_t)N);
+      for (int32_t k = 0; k < N; k++) {
+        int32_t c = straight_coord(N, asc, k);
+        for (int32_t xp = 0; xp < N; xp++) {
+          int32_t i, j;
+          straight_cell(p, tb, T, xp, c, &i, &j);
+          size_t x = cell_index(p, i, j, T);
+          uint8_t r = (uint8_t)((carry[xp] | R[x]) & (B[x] != OR_HARD));
+          out[x] |= r;
+          carry[xp] = r;
+        }
+      }
+    }
+    free(carry);
+  }
+}
+
+/* level: N_R bytes out.  Start must be free (OR_ESTART otherwise); 0 <=
+ * n_cycles <= 254. */
+int or_reach(const or_problem* p, const uint8_t* B, int32_t si, int32_t sj, int32_t st, int32_t n_cycles,
+             uint8_t* level) {
+  int rc = check_problem(p);
+  if (rc) return rc;
+  if (n_cycles < 0 || n_cycles > 254) return OR_EINVAL;
+  if (si < 0 || sj < 0 || st < 0 || si >= p->nx || sj >= p->nx || st >= p->nt) return OR_EINVAL;
+  size_t NR = (size_t)p->nx * p->nx * p->nt, x0 = cell_index(p, si, sj, st);
+  if (B[x0] == OR_HARD) return OR_ESTART;
+  or_tables tb;
+  rc = tables_build(p, &tb);
+  uint8_t* R = (uint8_t*)calloc(NR, 1);
+  uint8_t* next = (uint8_t*)calloc(NR, 1);
+  if (rc == OR_OK && (!R || !next)) rc = OR_ENOMEM;
+  if (rc == OR_OK) {
+    memset(level, 255, NR);
+    R[x0] = 1;
+    level[x0] = 0;
+    for (int32_t m = 0; m < n_cycles; m++) {
+      memset(next, 0, NR);
+      for (int32_t k = 0; k < p->nsched; k++) {
+        int mu = p->sched[k];
+        if (is_turn(mu))
+          reach_turn(p, &tb, mu, B, R, next);
+        else
+          reach_straight(p, &tb, mu, B, R, next);
+      }
+      for (size_t x = 0; x < NR; x++)
+        if (next[x] && level[x] == 255) level[x] = (uint8_t)(m + 1);
+      uint8_t* t = R;
+      R = next;
+      next = t;
+    }
+  }
+  free(R);
+  free(next);
+  tables_free(&tb);
+  return rc;
+}
+
+/* Goal search on levels: among the vertices within max-norm distance d of
+ * the goal (coordinates modulo their dimension) with a level, the smallest
+ * (level, |dx|+|dy|+|dT|, dT, dy, dx). */
+int or_reach_goal(const or_problem* p, const uint8_t* level, int32_t gi, int32_t gj, int32_t gt, int32_t d,
+                  int32_t* best, int32_t* best_level) {
+  int rc = check_problem(p);
+  if (rc) return rc;
+  if (d < 0 || gi < 0 || gj < 0 || gt < 0 || gi >= p->nx || gj >= p->nx || gt >= p->nt) return OR_EINVAL;
+  int found = 0;
+  int32_t bl = 0, bm = 0, bt = 0, by = 0, bx = 0;
+  for (int32_t dt = -d; dt <= d; dt++)
+    for (int32_t dy = -d; dy <= d; dy++)
+      for (int32_t dx = -d; dx <= d; dx++) {
+        int32_t i = wrap((int64_t)gi + dx, p->nx), j = wrap((int64_t)gj + dy, p->nx);
+        int32_t T = wrap((int64_t)gt + dt, p->nt);
+        int32_t l = level[cell_index(p, i, j, T)];
+        if (l == 255) continue;
+        int32_t m = abs(dx) + abs(dy) + abs(dt);
+        int better = !found || l < bl ||
+                     (l == bl && (m < bm || (m == bm && (dt < bt || (dt == bt && (dy < by || (dy == by && dx < bx)))))));
+        if (better) {
+          found = 1;
+          bl = l;
+          bm = m;
+          bt = dt;
+          by = dy;
+          bx = dx;
+          best[0] = i;
+          best[1] = j;
+          best[2] = T;
+        }
+      }
+  if (!found) return OR_EUNREACH;
+  *best_level = bl;
+  return OR_OK;
+}
+
+/* Back-tracking on levels: from a vertex of level m >= 1, the first
+ * scheduled maneuver (in schedule order) with a vertex p_k, k steps up its
+ * curve through free vertices, of level m - 1, nearest first; that vertex
+ * becomes the current one.  Every step is one maneuver (cost 1).  Steps come
+ * out start -> goal. */
+int or_reach_backtrack(const or_problem* p, const uint8_t* B, const uint8_t* level, const int32_t* goal,
+                       or_step* steps, int32_t cap, int32_t* n_steps) {
+  int rc = check_problem(p);
+  if (rc) return rc;
+  int32_t N = p->nx, L = p->nt;
+  or_tables tb;
+  rc = tables_build(p, &tb);
+  if (rc) {
+    tables_free(&tb);
+    return rc;
+  }
+  int32_t ci = goal[0], cj = goal[1], cT = goal[2];
+  int32_t n = 0;
+  int32_t m = level[cell_index(p, ci, cj, cT)];
+  if (m == 255) rc = OR_EUNREACH;
+  int32_t maxk = N > L ? N : L;
+  while (rc == OR_OK && m > 0) {
+    int32_t bk = 0, bi = 0, bj = 0, bT = 0, bmu = -1;
+    for (int32_t pos = 0; pos < p->nsched && bmu < 0; pos++) {
+      int mu = p->sched[pos];
+      for (int32_t k = 1; k <= maxk; k++) {
+        int32_t qi, qj, qT;
+        if (!predecessor(p, &tb, mu, ci, cj, cT, k, &qi, &qj, &qT)) break;
+        size_t q = cell_index(p, qi, qj, qT);
+        if (B[q] == OR_HARD) break; /* a hard vertex ends the curve */
+        if (level[q] == m - 1) {
+          bk = k;
+          bmu = mu;
+          bi = qi;
+          bj = qj;
+          bT = qT;
+          break;
+        }
+      }
+    }
+    if (bmu < 0) {
+      rc = OR_EUNREACH; /* cannot happen for levels made by or_reach */
+      break;
+    }
+    if (n < cap) {
+      or_step* sp = &steps[n];
+      memset(sp, 0, sizeof(*sp));
+      sp->maneuver = (uint8_t)bmu;
+      sp->steps = (uint32_t)bk;
+      sp->from[0] = (uint32_t)bi;
+      sp->from[1] = (uint32_t)bj;
+      sp->from[2] = (uint32_t)bT;
+      sp->to[0] = (uint32_t)ci;
+      sp->to[1] = (uint32_t)cj;
+      sp->to[2] = (uint32_t)cT;
+      sp->cost = 1;
+    }
+    n++;
+    ci = bi;
+    cj = bj;
+    cT = bT;
+    m--;
+  }
+  tables_free(&tb);
+  *n_steps = n;
+  if (rc) return rc;
+  if (n > cap) return OR_ECAP;
+  for (int32_t a = 0, b = n - 1; a < b; a++, b--) {
     or_step t = steps[a];
     steps[a] = steps[b];
     steps[b] = t;
