@@ -122,7 +122,11 @@ int plan_set_cspace(nhp_plan* plan, const uint8_t* d_cspace);
 
 /* Sets V = NHP_INF everywhere and V(start) = 0, then runs n_cycles cycles of
  * the schedule, each maneuver kernel relaxing every pose once (Insert 1; turn
- * curves are cyclic and closed exactly, straights start at the wall).
+ * curves are cyclic and closed exactly, straights start at the wall).  Two
+ * consecutive turn maneuvers on the same circles in opposite directions
+ * (RB, RF or LB, LF in either order, also the last of one cycle and the
+ * first of the next) share one pass over the volume, with the result of
+ * running them one after the other.
  * Errors: NHP_ESTATE (no obstacle volume), NHP_EINVAL, NHP_ESTART (start in
  * collision; checked on the host, which synchronises once), NHP_EHIP. */
 int sweep_n_turns(nhp_plan* plan, uint32_t si, uint32_t sj, uint32_t st, uint32_t n_cycles);
@@ -135,6 +139,24 @@ int sweep_resume(nhp_plan* plan, uint32_t n_more_cycles);
 /* One maneuver kernel (Insert 1 over every curve of `maneuver`) on the
  * current value volume, whatever it holds.  Errors: NHP_ESTATE, NHP_EINVAL. */
 int sweep_one(nhp_plan* plan, uint32_t maneuver);
+
+/* Maneuver `first` then maneuver `second` (-1: none) on the current value
+ * volume.  When the two are turns on the same circles in opposite directions
+ * and the plan's curves fit the fused kernel, both run in one pass (one read
+ * and one write per pose); otherwise as two sweep_one calls.  Same result
+ * either way.  Errors: NHP_ESTATE, NHP_EINVAL. */
+int sweep_pass(nhp_plan* plan, int32_t first, int32_t second);
+
+/* Host only (no device work): the passes that sweeps n_steps sweeps of a
+ * schedule starting at sweep number first_step (sweep k applies
+ * schedule[k % n_schedule]) are grouped into, as sweep_n_turns and
+ * batch_advance group them: with pairs != 0, consecutive turns on the same
+ * circles in opposite directions share a pass, paired greedily from the
+ * first.  Pass k is first[k] then second[k] (-1: none).  *n_passes is always
+ * set; NHP_ECAP when it exceeds cap (arrays untouched), NHP_EINVAL for a bad
+ * schedule. */
+int schedule_passes(const uint8_t* schedule, uint32_t n_schedule, uint64_t first_step, uint64_t n_steps,
+                    int32_t pairs, int8_t* first, int8_t* second, uint32_t cap, uint32_t* n_passes);
 
 /* Goal search (Sec. IX) then back-tracking (Sec. X, eq. 32), both on the
  * device; only the plan crosses to the host.
@@ -204,9 +226,18 @@ int batch_init(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* starts_
  * sweep_n_turns yet), NHP_EINVAL. */
 int batch_step(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* steps, uint32_t n);
 
-/* batch_init, then step s = 0, 1, ... covering every plan k with
- * s < n_cycles[k] * n_schedule: plan k ends with n_cycles[k] cycles, as
- * sweep_n_turns would leave it. */
+/* Several ticks at once: plan k runs its sweeps steps[k] .. steps[k] +
+ * counts[k] - 1 (counts[k] = 0: none).  Consecutive turn sweeps on the same
+ * circles in opposite directions (RB then RF, LB then LF, and the reverse
+ * orders) share one pass over the volume, with the same result as two
+ * batch_step calls; pass t of every plan goes into shared launches (at most
+ * nine per pass).  Errors as batch_step. */
+int batch_advance(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* steps, const uint32_t* counts,
+                  uint32_t n);
+
+/* batch_init, then batch_advance from step 0 by n_cycles[k] * n_schedule
+ * sweeps: plan k ends with n_cycles[k] cycles, as sweep_n_turns would leave
+ * it. */
 int batch_sweep(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* starts_ijt,
                 const uint32_t* n_cycles, uint32_t n);
 
@@ -232,6 +263,63 @@ int nhp_set_section_steps(uint32_t curve_len, uint32_t steps);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* plan_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Reachability by maneuver count (App. C, Insert 2; Sections of App. D).
+ * Hard obstacles only (image code 255; every other code is free), every
+ * maneuver costs one and moves cost nothing: bit volumes say, per pose,
+ * whether it can be reached with at most m maneuvers, for m = 0..n_cycles.
+ * Bit layout: 32-bit word ((T * nx + j) * nx/32 + i/32), bit i % 32; in the
+ * level volumes a set bit means NOT reachable (the paper's convention), in
+ * the obstacle volume a set bit means hard.  Each cycle applies every
+ * scheduled maneuver to R_m and ANDs the results into R_{m+1}; the schedule
+ * order does not matter.  The state uses its plan's tables and stream; it
+ * must be destroyed before the plan.
+ * ------------------------------------------------------------------- */
+typedef struct nhp_reach nhp_reach;
+
+/* Device bytes of a reachability state keeping max_cycles + 1 level volumes
+ * (nx^2 ntheta / 8 bytes each) plus the obstacle bits; 0 when the sizes are
+ * not supported (nx a multiple of 32 in [32, 512], ntheta <= 512, 1 <=
+ * max_cycles <= 254). */
+size_t reach_workspace_bytes(const nhp_params* params, uint32_t max_cycles);
+
+/* d_workspace: 256-byte aligned device memory of at least
+ * reach_workspace_bytes, or NULL for a library allocation.  Errors:
+ * NHP_EINVAL (sizes, workspace), NHP_ENOMEM. */
+int reach_create(nhp_plan* plan, uint32_t max_cycles, void* d_workspace, size_t workspace_bytes,
+                 nhp_reach** out);
+int reach_destroy(nhp_reach* reach);
+
+/* Obstacle bits: the hard cells of the image (nx*nx codes, device memory)
+ * dilated by the vehicle box exactly as render_cspace does (so a pose is
+ * hard here exactly when render_cspace gives it code 255); walls at i = 0
+ * and j = 0 hard. */
+int reach_render(nhp_reach* reach, const uint8_t* d_image, int32_t front, int32_t rear, int32_t half_width);
+
+/* Obstacle bits from an obstacle code volume (device, nx*nx*ntheta codes;
+ * 255 = hard), walls forced hard. */
+int reach_set_cspace(nhp_reach* reach, const uint8_t* d_codes);
+
+/* R_0 = {start}, then n_cycles cycles (n_cycles <= max_cycles).  Errors:
+ * NHP_ESTATE (no obstacle bits), NHP_EINVAL, NHP_ESTART (start hard;
+ * checked on the host, which synchronises once). */
+int reach_sweep(nhp_reach* reach, uint32_t si, uint32_t sj, uint32_t st, uint32_t n_cycles);
+
+/* Goal search and back-tracking on the levels: within max-norm radius of the
+ * goal (coordinates modulo their dimension) the pose with the smallest
+ * (level, |dx|+|dy|+|dT|, dT, dy, dx); then from a pose of level m, for the
+ * scheduled maneuvers in schedule order, the nearest pose up the curve
+ * (through free poses) of level m - 1, until level 0.  *level = the best
+ * pose's level = the number of steps (each cost_q10 = 1).  Synchronises.
+ * Errors: NHP_EUNREACH, NHP_ECAP (*n_steps still set), NHP_EINVAL,
+ * NHP_ESTATE. */
+int reach_extract(nhp_reach* reach, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t radius, nhp_step* h_steps,
+                  uint32_t cap, uint32_t* n_steps, uint32_t* best_ijt, uint32_t* level);
+
+/* Device pointers of the obstacle bits and of level volume 0 (volume m
+ * follows at m * nx^2 ntheta / 32 words), for checking and checkpoints. */
+int reach_device_ptrs(const nhp_reach* reach, uint32_t** d_hard, uint32_t** d_levels);
 
 #ifdef __cplusplus
 }

@@ -263,7 +263,134 @@ __global__ __launch_bounds__(kThreads) void extract_batch_kernel(const ExArgs* _
   extract_body(x, red32, red64);
 }
 
+// ---- reachability (App. C): goal search and back-tracking on level bits ----
+
+__device__ __forceinline__ bool reach_bit(const ReachExArgs& x, int m, int i, int j, int T) {
+  const int N = x.d.nx;
+  const uint32_t word = x.levels[(size_t)m * x.vol_words + ((size_t)T * N + j) * x.W + (i >> 5)];
+  return ((word >> (i & 31)) & 1u) == 0u;  // a clear bit is reachable
+}
+
+__device__ __forceinline__ bool hard_bit(const ReachExArgs& x, int i, int j, int T) {
+  const int N = x.d.nx;
+  return (x.hard[((size_t)T * N + j) * x.W + (i >> 5)] >> (i & 31)) & 1u;
+}
+
+// smallest m with the pose reachable (levels are nested), or -1
+__device__ int pose_level(const ReachExArgs& x, int i, int j, int T) {
+  int hi = x.n_levels - 1;
+  if (!reach_bit(x, hi, i, j, T)) return -1;
+  int lo = 0;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (reach_bit(x, mid, i, j, T))
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+// Goal window: smallest (level, |dx|+|dy|+|dT|, dT, dy, dx).  Back-tracking
+// from a pose of level m: for the scheduled maneuvers in schedule order, the
+// nearest pose up the curve (through free poses) of level m - 1.
+__global__ __launch_bounds__(kThreads) void reach_extract_kernel(ReachExArgs x) {
+  __shared__ uint64_t red64[kWaves];
+  __shared__ int first_hard[6];
+  const DevPlan& d = x.d;
+  const int N = d.nx, L = d.nt;
+  const int tid = threadIdx.x;
+  uint32_t* out = x.out;
+  const int r = x.radius, Wd = 2 * r + 1, nc = Wd * Wd * Wd;
+  uint64_t key = ~0ull;
+  for (int c = tid; c < nc; c += kThreads) {
+    const int dx = c % Wd - r, dy = (c / Wd) % Wd - r, dt = c / (Wd * Wd) - r;
+    const int i = modn((int)x.gi + dx, N), j = modn((int)x.gj + dy, N), T = modn((int)x.gt + dt, L);
+    const int lv = pose_level(x, i, j, T);
+    if (lv < 0) continue;
+    const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy, at = dt < 0 ? -dt : dt;
+    const uint64_t k2 = ((uint64_t)lv << 25) | ((uint64_t)(ax + ay + at) << 18) | ((uint64_t)(dt + r) << 12) |
+                        ((uint64_t)(dy + r) << 6) | (uint64_t)(dx + r);
+    key = k2 < key ? k2 : key;
+  }
+  key = block_min_u64(key, red64);
+  if (key == ~0ull) {
+    if (tid == 0) {
+      out[0] = (uint32_t)(-NHP_EUNREACH);
+      out[1] = 0;
+    }
+    return;
+  }
+  int ci = modn((int)x.gi + (int)(key & 63) - r, N);
+  int cj = modn((int)x.gj + (int)((key >> 6) & 63) - r, N);
+  int cT = modn((int)x.gt + (int)((key >> 12) & 63) - r, L);
+  int m = (int)(key >> 25);
+  if (tid == 0) {
+    out[2] = ci;
+    out[3] = cj;
+    out[4] = cT;
+    out[5] = m;
+  }
+  uint32_t n = 0, status = 0;
+  const int k = tid + 1;
+  while (m > 0) {
+    if (tid < 6) first_hard[tid] = 0x7fffffff;
+    __syncthreads();
+    int pi[6], pj[6], pT[6];
+    bool ok[6];
+#pragma unroll
+    for (int pos = 0; pos < 6; pos++) {
+      ok[pos] = pos < d.n_schedule && predecessor(d, d.schedule[pos], ci, cj, cT, k, &pi[pos], &pj[pos], &pT[pos]);
+      if (ok[pos] && hard_bit(x, pi[pos], pj[pos], pT[pos])) atomicMin(&first_hard[pos], k);
+    }
+    __syncthreads();
+    uint64_t best = ~0ull;
+#pragma unroll
+    for (int pos = 0; pos < 6; pos++) {
+      if (ok[pos] && k < first_hard[pos] && reach_bit(x, m - 1, pi[pos], pj[pos], pT[pos])) {
+        const uint64_t k2 = ((uint64_t)pos << 11) | (uint64_t)k;
+        best = k2 < best ? k2 : best;
+      }
+    }
+    best = block_min_u64(best, red64);
+    if (best == ~0ull) {
+      status = (uint32_t)(-NHP_EUNREACH);
+      break;
+    }
+    const int pos = (int)(best >> 11), kb = (int)(best & 2047);
+    const int mu = d.schedule[pos];
+    int qi, qj, qT;
+    predecessor(d, mu, ci, cj, cT, kb, &qi, &qj, &qT);
+    if (tid == 0 && n < (uint32_t)kReachMaxSteps) {
+      uint32_t* st = out + kExHeader + (size_t)n * kExStepWords;
+      st[0] = mu;
+      st[1] = kb;
+      st[2] = qi;
+      st[3] = qj;
+      st[4] = qT;
+      st[5] = ci;
+      st[6] = cj;
+      st[7] = cT;
+      st[8] = 1;
+    }
+    n++;
+    ci = qi;
+    cj = qj;
+    cT = qT;
+    m--;
+  }
+  if (tid == 0) {
+    out[0] = status;
+    out[1] = n;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_reach_extract(const ReachExArgs& x, hipStream_t s) {
+  hipLaunchKernelGGL(reach_extract_kernel, dim3(1), dim3(kThreads), 0, s, x);
+  return hipGetLastError();
+}
 
 hipError_t launch_extract(const DevPlan& d, uint32_t si, uint32_t sj, uint32_t st, uint32_t gi, uint32_t gj,
                           uint32_t gt, int radius, uint32_t w_xy, uint32_t w_t, hipStream_t s) {

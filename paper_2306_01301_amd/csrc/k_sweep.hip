@@ -64,16 +64,25 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 }
 
 // Value entering this wave's section: the cyclic fixed point (turns) or the
-// composition of the earlier sections from INF (straights).
+// composition of the earlier sections from INF (straights).  Sections are
+// visited in increasing order (forward) or decreasing order (the second
+// maneuver of a fused pair, which walks the curves backwards).
+template <bool BACKWARD = false>
 __device__ __forceinline__ uint32_t section_carry(const uint32_t (*aggD)[64], const uint32_t (*aggC)[64], int S,
                                                   int wave, int lane, bool cyclic) {
   uint32_t C = kInf;
   if (cyclic) {
+    // once around, starting with this section and ending with the one before it
     int s = wave;
     for (int t = 0; t < S; t++) {
       C = umin(sadd(C, aggD[s][lane]), aggC[s][lane]);
-      s = (s + 1 == S) ? 0 : s + 1;
+      if (BACKWARD)
+        s = (s == 0) ? S - 1 : s - 1;
+      else
+        s = (s + 1 == S) ? 0 : s + 1;
     }
+  } else if (BACKWARD) {
+    for (int s = S - 1; s > wave; s--) C = umin(sadd(C, aggD[s][lane]), aggC[s][lane]);
   } else {
     for (int s = 0; s < wave; s++) C = umin(sadd(C, aggD[s][lane]), aggC[s][lane]);
   }
@@ -83,7 +92,10 @@ __device__ __forceinline__ uint32_t section_carry(const uint32_t (*aggD)[64], co
 struct RowShared {
   uint32_t aggD[16][64];
   uint32_t aggC[16][64];
+  uint32_t aggD2[16][64];  // second maneuver of a fused pair
+  uint32_t aggC2[16][64];
   uint32_t wlut[256];      // edge weight by obstacle code (INF for hard)
+  uint32_t wlut2[256];     // the same for the second maneuver
   uint32_t row_base[1024]; // per step: index of the first pose of the row it reads
   uint16_t shift[1024];    // per step: column offset of curve x' (reduced mod N)
 };
@@ -92,7 +104,10 @@ struct RowShared {
 // y-major straights.
 //   turns:     tile -> (x tile, y'); step k -> plane T_k, offsets (ox, oy)
 //   straights: tile -> (x tile, plane slot); step k -> row c_k, column x' + B(c_k)
-template <int P>
+// FUSED (turns): after the first maneuver the second one, on the same curves
+// in the opposite direction, runs on the values still held in registers, so
+// the pair costs one read and one write per pose.
+template <int P, bool FUSED>
 __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowShared& sh) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -115,7 +130,10 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
     dir = (a.fwd[T0] > 0) == (a.mu_forward != 0);
     sk = a.skew + (size_t)T0 * N;
   }
-  for (int c = threadIdx.x; c < 256; c += blockDim.x) sh.wlut[c] = weight((uint32_t)c, 256u * Lq + 128u, 4u * Lq);
+  for (int c = threadIdx.x; c < 256; c += blockDim.x) {
+    sh.wlut[c] = weight((uint32_t)c, 256u * Lq + 128u, 4u * Lq);
+    if (FUSED) sh.wlut2[c] = weight((uint32_t)c, 256u * a.lq2 + 128u, 4u * a.lq2);
+  }
   // Step s of a curve touches row `row` of plane T at column (x' + shift)
   // mod N: a row base shared by the 64 lanes plus a small per-lane column.
   // The geometry of all steps goes to LDS once per workgroup.
@@ -140,6 +158,7 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
 
   uint32_t u[P];
   uint32_t code[P];
+  uint32_t packed[FUSED ? P / 4 : 1];
   // Sections are P steps; steps past the curve length (when S P > L) are
   // identity maps that touch no memory.
   const int n_real = (L - wave * P) < P ? (L - wave * P) : P;  // real steps of this wave
@@ -162,8 +181,16 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
   }
   if (busy) {
     // weights replace the codes; compose the section into (D, C):
-    // min(C + w, u + ct + w) = min(C, u + ct) + w (saturating add is monotone)
+    // min(C + w, u + ct + w) = min(C, u + ct) + w (saturating add is monotone).
+    // A fused pair keeps the codes, packed four to a register, for the
+    // second maneuver's weights (packing after the loads have landed, so it
+    // does not hold the loads back).
     uint32_t D = 0, C = kInf;
+    if (FUSED) {
+#pragma unroll
+      for (int q = 0; q < P / 4; q++)
+        packed[q] = code[4 * q] | (code[4 * q + 1] << 8) | (code[4 * q + 2] << 16) | (code[4 * q + 3] << 24);
+    }
 #pragma unroll
     for (int k = 0; k < P; k++) code[k] = sh.wlut[code[k]];
 #pragma unroll
@@ -188,6 +215,38 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
       u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
       v = sadd(umin(v, sadd(uu, a.ct)), w);
     }
+    if (FUSED) {
+      // second maneuver: the steps of the section in reverse order, its
+      // weights replacing the codes
+      uint32_t D2 = 0, C2 = kInf;
+#pragma unroll
+      for (int k = P - 1; k >= 0; k--) {
+        if (k < n_real) {
+          code[k] = sh.wlut2[(packed[k >> 2] >> (8 * (k & 3))) & 0xffu];
+          C2 = sadd(umin(C2, sadd(u[k], a.ct2)), code[k]);
+          D2 = sadd(D2, code[k]);
+        }
+      }
+      sh.aggD2[wave][lane] = D2;
+      sh.aggC2[wave][lane] = C2;
+    }
+  }
+  if (FUSED) {
+    __syncthreads();
+    if (busy) {
+      uint32_t v = section_carry<true>(sh.aggD2, sh.aggC2, S, wave, lane, cyclic);
+#pragma unroll
+      for (int k = P - 1; k >= 0; k--) {
+        if (k < n_real) {
+          const uint32_t w = code[k];
+          const uint32_t uu = u[k];
+          u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+          v = sadd(umin(v, sadd(uu, a.ct2)), w);
+        }
+      }
+    }
+  }
+  if (busy) {
     // recompute the column of every step rather than keeping P of them live
     int xs = xp;
     asm volatile("" : "+v"(xs));
@@ -352,19 +411,19 @@ __device__ __forceinline__ int find_job(const SweepJob* __restrict__ jobs, int n
   return lo;
 }
 
-template <int P>
+template <int P, bool FUSED>
 __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepJob job) {
   __shared__ RowShared sh;
-  row_sweep_tile<P>(job, xcd_tile(blockIdx.x, gridDim.x), sh);
+  row_sweep_tile<P, FUSED>(job, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
 
-template <int P>
+template <int P, bool FUSED>
 __global__ __launch_bounds__(1024) void row_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs) {
   __shared__ RowShared sh;
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
   const SweepJob job = jobs[j];
-  row_sweep_tile<P>(job, t - job.first_block, sh);
+  row_sweep_tile<P, FUSED>(job, t - job.first_block, sh);
 }
 
 template <int Q>
@@ -457,10 +516,33 @@ int set_section_steps(int len, int P) {
   return NHP_OK;
 }
 
-// The jobs of one maneuver of one plan: a row job (turns, or the y-major
+void schedule_passes(const uint8_t* schedule, int n, uint64_t first, uint64_t count, bool pairs,
+                     std::vector<Pass>& out) {
+  const uint64_t end = first + count;
+  for (uint64_t k = first; k < end;) {
+    const int a = schedule[k % (uint64_t)n];
+    if (pairs && k + 1 < end && fusable(a, schedule[(k + 1) % (uint64_t)n])) {
+      out.push_back(Pass{(int8_t)a, (int8_t)schedule[(k + 1) % (uint64_t)n]});
+      k += 2;
+    } else {
+      out.push_back(Pass{(int8_t)a, (int8_t)-1});
+      k += 1;
+    }
+  }
+}
+
+bool can_fuse(const DevPlan& d) {
+  const int P = pick_section(d.nt);
+  return P > 0 && P <= 32;
+}
+
+// The jobs of one pass of one plan: a row job (turns, or the y-major
 // straight planes) and, for straights, an x-major job.  Returns the number of
-// jobs written (0..2); blocks counts each job's workgroups.
-int make_sweep_jobs(const DevPlan& d, int mu, SweepJob* row, SweepJob* xmaj) {
+// jobs written (0..2), blocks counts each job's workgroups; -1 for a pair
+// that cannot share a pass (the caller splits it).
+int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj) {
+  if (pass.mu2 >= 0 && !(fusable(pass.mu, pass.mu2) && can_fuse(d))) return -1;
+  const int mu = pass.mu;
   const int N = d.nx, L = d.nt;
   const int tiles_x = (N + 63) / 64;
   SweepJob j{};
@@ -498,6 +580,12 @@ int make_sweep_jobs(const DevPlan& d, int mu, SweepJob* row, SweepJob* xmaj) {
     j.offy = d.turn_off + (left ? 1 : 3) * L;
     j.lq = d.turn_lq[mu];
     j.P = pick_section(L);
+    if (pass.mu2 >= 0) {
+      if (j.P > 32) return -1;  // tuning changed since can_fuse
+      j.fused = 1;
+      j.ct2 = d.ct[pass.mu2];
+      j.lq2 = d.turn_lq[pass.mu2];
+    }
     j.blocks = tiles_x * N;
     *row = j;
     xmaj->blocks = 0;
@@ -506,16 +594,24 @@ int make_sweep_jobs(const DevPlan& d, int mu, SweepJob* row, SweepJob* xmaj) {
   return n;
 }
 
-hipError_t launch_row_job(const SweepJob& j, hipStream_t s) {
+template <bool FUSED>
+hipError_t launch_row_job_t(const SweepJob& j, hipStream_t s) {
   const dim3 grid(j.blocks), block(64 * ((j.L + j.P - 1) / j.P));
   switch (j.P) {
-    case 64: hipLaunchKernelGGL(row_sweep_kernel<64>, grid, block, 0, s, j); break;
-    case 32: hipLaunchKernelGGL(row_sweep_kernel<32>, grid, block, 0, s, j); break;
-    case 16: hipLaunchKernelGGL(row_sweep_kernel<16>, grid, block, 0, s, j); break;
-    case 8: hipLaunchKernelGGL(row_sweep_kernel<8>, grid, block, 0, s, j); break;
+    case 64:
+      if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
+      hipLaunchKernelGGL((row_sweep_kernel<64, false>), grid, block, 0, s, j);
+      break;
+    case 32: hipLaunchKernelGGL((row_sweep_kernel<32, FUSED>), grid, block, 0, s, j); break;
+    case 16: hipLaunchKernelGGL((row_sweep_kernel<16, FUSED>), grid, block, 0, s, j); break;
+    case 8: hipLaunchKernelGGL((row_sweep_kernel<8, FUSED>), grid, block, 0, s, j); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_row_job(const SweepJob& j, hipStream_t s) {
+  return j.fused ? launch_row_job_t<true>(j, s) : launch_row_job_t<false>(j, s);
 }
 
 hipError_t launch_init(const DevPlan& d, uint32_t start_index, hipStream_t s) {
@@ -539,9 +635,13 @@ hipError_t launch_force_walls(const DevPlan& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(const DevPlan& d, int mu, hipStream_t s) {
+hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s) {
   SweepJob row{}, xmaj{};
-  make_sweep_jobs(d, mu, &row, &xmaj);
+  if (make_sweep_jobs(d, pass, &row, &xmaj) < 0) {
+    // a pair that cannot share a pass: one pass each
+    const hipError_t e = launch_sweep(d, Pass{pass.mu, (int8_t)-1}, s);
+    return e != hipSuccess ? e : launch_sweep(d, Pass{pass.mu2, (int8_t)-1}, s);
+  }
   if (row.blocks) {
     if (!row.P) return hipErrorInvalidValue;
     const hipError_t e = launch_row_job(row, s);
@@ -554,23 +654,31 @@ hipError_t launch_sweep(const DevPlan& d, int mu, hipStream_t s) {
   return hipSuccess;
 }
 
-hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool xmajor,
-                              hipStream_t s) {
-  if (n_jobs == 0) return hipSuccess;
-  const dim3 grid(total_blocks);
-  if (xmajor) {
-    hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ>), grid, dim3(256), 0, s, d_jobs, n_jobs);
-    return hipGetLastError();
-  }
-  const dim3 block(1024);
+template <bool FUSED>
+hipError_t launch_row_batch_t(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, hipStream_t s) {
+  const dim3 grid(total_blocks), block(1024);
   switch (P) {
-    case 64: hipLaunchKernelGGL(row_sweep_batch_kernel<64>, grid, block, 0, s, d_jobs, n_jobs); break;
-    case 32: hipLaunchKernelGGL(row_sweep_batch_kernel<32>, grid, block, 0, s, d_jobs, n_jobs); break;
-    case 16: hipLaunchKernelGGL(row_sweep_batch_kernel<16>, grid, block, 0, s, d_jobs, n_jobs); break;
-    case 8: hipLaunchKernelGGL(row_sweep_batch_kernel<8>, grid, block, 0, s, d_jobs, n_jobs); break;
+    case 64:
+      if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
+      hipLaunchKernelGGL((row_sweep_batch_kernel<64, false>), grid, block, 0, s, d_jobs, n_jobs);
+      break;
+    case 32: hipLaunchKernelGGL((row_sweep_batch_kernel<32, FUSED>), grid, block, 0, s, d_jobs, n_jobs); break;
+    case 16: hipLaunchKernelGGL((row_sweep_batch_kernel<16, FUSED>), grid, block, 0, s, d_jobs, n_jobs); break;
+    case 8: hipLaunchKernelGGL((row_sweep_batch_kernel<8, FUSED>), grid, block, 0, s, d_jobs, n_jobs); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool xmajor,
+                              hipStream_t s) {
+  if (n_jobs == 0) return hipSuccess;
+  if (xmajor) {
+    hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ>), dim3(total_blocks), dim3(256), 0, s, d_jobs, n_jobs);
+    return hipGetLastError();
+  }
+  return fused ? launch_row_batch_t<true>(d_jobs, n_jobs, total_blocks, P, s)
+               : launch_row_batch_t<false>(d_jobs, n_jobs, total_blocks, P, s);
 }
 
 }  // namespace nhp

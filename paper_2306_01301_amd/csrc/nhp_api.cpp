@@ -217,7 +217,9 @@ int plan_create(const nhp_params* params, void* d_workspace, size_t workspace_by
 int plan_destroy(nhp_plan* plan) {
   if (!plan) return ok();
   (void)hipStreamSynchronize(plan->stream);
-  if (plan->cycle) (void)hipGraphExecDestroy(plan->cycle);
+  for (auto& row : plan->cycle)
+    for (hipGraphExec_t g : row)
+      if (g) (void)hipGraphExecDestroy(g);
   if (plan->own_ws && plan->ws) (void)hipFree(plan->ws);
   delete plan;
   return ok();
@@ -281,38 +283,63 @@ int plan_set_cspace(nhp_plan* plan, const uint8_t* d_cspace) {
   return ok();
 }
 
-// Captures one cycle of the schedule (all its launches) into a graph on a
-// private stream; the graph depends only on the plan's fixed device state,
-// so it is replayed on whatever stream the plan uses.
-static void capture_cycle(nhp_plan* plan) {
+// The passes of one cycle of the schedule.  skip_first: the previous
+// cycle's last pass already applied schedule[0].  pair_next: the cycle's last
+// sweep may share a pass with the next cycle's first.  Returns whether it did.
+static bool cycle_passes(const nhp_params& p, bool skip_first, bool pair_next, bool pairs,
+                         std::vector<nhp::Pass>& out) {
+  const uint64_t m = (uint64_t)p.n_schedule, first = skip_first ? 1 : 0;
+  nhp::schedule_passes(p.schedule, (int)m, first, m - first + (pair_next ? 1 : 0), pairs, out);
+  if (!pair_next || !pairs) return false;
+  // the extra step is the next cycle's first sweep: keep it only inside a pair
+  if (out.back().mu2 >= 0) return true;
+  out.pop_back();
+  return false;
+}
+
+// Captures the launches of one cycle into a graph on a private stream; the
+// graph depends only on the plan's fixed device state, so it is replayed on
+// whatever stream the plan uses.
+static hipGraphExec_t capture_passes(nhp_plan* plan, const std::vector<nhp::Pass>& passes) {
   hipStream_t cs = nullptr;
   hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
   bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
             hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
-    for (int k = 0; k < plan->p.n_schedule; k++)
-      ok = ok && nhp::launch_sweep(plan->d, plan->p.schedule[k], cs) == hipSuccess;
+    for (const nhp::Pass& q : passes) ok = ok && nhp::launch_sweep(plan->d, q, cs) == hipSuccess;
     ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok && g != nullptr;
   }
-  if (ok) ok = hipGraphInstantiate(&plan->cycle, g, nullptr, nullptr, 0) == hipSuccess;
+  if (ok) ok = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
   if (g) (void)hipGraphDestroy(g);
   if (cs) (void)hipStreamDestroy(cs);
   if (!ok) {
-    plan->cycle = nullptr;
+    exec = nullptr;
     plan->graph_failed = true;
     (void)hipGetLastError();  // clear a sticky capture error
   }
+  return exec;
 }
 
+// n_cycles cycles of the schedule as passes (consecutive turns on shared
+// curves fused, also across cycle boundaries).  A cycle's launches come from
+// a captured graph once the call runs more than one cycle.
 static int run_cycles(nhp_plan* plan, uint32_t n_cycles) {
-  if (n_cycles > 1 && !plan->cycle && !plan->graph_failed) capture_cycle(plan);
+  const bool pairs = nhp::can_fuse(plan->d);
+  bool skip = false;
+  std::vector<nhp::Pass> passes;
   for (uint32_t n = 0; n < n_cycles; n++) {
-    if (plan->cycle) {
-      HIP_CHECK(hipGraphLaunch(plan->cycle, plan->stream), "cycle graph launch");
-      continue;
+    const bool pair_next = n + 1 < n_cycles;
+    passes.clear();
+    const bool consumed = cycle_passes(plan->p, skip, pair_next, pairs, passes);
+    hipGraphExec_t& g = plan->cycle[skip][pair_next];
+    if (n_cycles > 1 && !g && !plan->graph_failed) g = capture_passes(plan, passes);
+    if (g) {
+      HIP_CHECK(hipGraphLaunch(g, plan->stream), "cycle graph launch");
+    } else {
+      for (const nhp::Pass& q : passes) HIP_CHECK(nhp::launch_sweep(plan->d, q, plan->stream), "sweep launch");
     }
-    for (int k = 0; k < plan->p.n_schedule; k++)
-      HIP_CHECK(nhp::launch_sweep(plan->d, plan->p.schedule[k], plan->stream), "sweep launch");
+    skip = consumed;
   }
   return NHP_OK;
 }
@@ -342,12 +369,38 @@ int sweep_resume(nhp_plan* plan, uint32_t n_more_cycles) {
   return (rc = run_cycles(plan, n_more_cycles)) ? rc : ok();
 }
 
+int sweep_pass(nhp_plan* plan, int32_t first, int32_t second) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!plan->has_cspace) return fail(NHP_ESTATE, "sweep_pass before render_cspace/plan_set_cspace");
+  if (first < 0 || first > 5 || second < -1 || second > 5) return fail(NHP_EINVAL, "maneuvers must be 0..5 (second: -1 for none)");
+  HIP_CHECK(nhp::launch_sweep(plan->d, nhp::Pass{(int8_t)first, (int8_t)second}, plan->stream), "sweep launch");
+  return ok();
+}
+
+int schedule_passes(const uint8_t* schedule, uint32_t n_schedule, uint64_t first_step, uint64_t n_steps,
+                    int32_t pairs, int8_t* first, int8_t* second, uint32_t cap, uint32_t* n_passes) {
+  if (!schedule || n_schedule < 1 || n_schedule > 6 || !n_passes) return fail(NHP_EINVAL, "bad schedule or NULL count");
+  for (uint32_t k = 0; k < n_schedule; k++)
+    if (schedule[k] > 5) return fail(NHP_EINVAL, "schedule entries must be 0..5");
+  std::vector<nhp::Pass> v;
+  nhp::schedule_passes(schedule, (int)n_schedule, first_step, n_steps, pairs != 0, v);
+  *n_passes = (uint32_t)v.size();
+  if (v.size() > cap) return fail(NHP_ECAP, "%zu passes, room for %u", v.size(), cap);
+  if (!v.empty() && (!first || !second)) return fail(NHP_EINVAL, "output arrays are NULL");
+  for (size_t k = 0; k < v.size(); k++) {
+    first[k] = v[k].mu;
+    second[k] = v[k].mu2;
+  }
+  return ok();
+}
+
 int sweep_one(nhp_plan* plan, uint32_t maneuver) {
   int rc = check_plan(plan);
   if (rc) return rc;
   if (!plan->has_cspace) return fail(NHP_ESTATE, "sweep_one before render_cspace/plan_set_cspace");
   if (maneuver > 5) return fail(NHP_EINVAL, "maneuver must be 0..5");
-  HIP_CHECK(nhp::launch_sweep(plan->d, (int)maneuver, plan->stream), "sweep launch");
+  HIP_CHECK(nhp::launch_sweep(plan->d, nhp::Pass{(int8_t)maneuver, (int8_t)-1}, plan->stream), "sweep launch");
   return ok();
 }
 

@@ -197,38 +197,35 @@ int batch_init(nhp_batch* b, nhp_plan* const* plans, const uint32_t* starts_ijt,
   return rc ? rc : nhp::clear_error();
 }
 
-int batch_step(nhp_batch* b, nhp_plan* const* plans, const uint32_t* steps, uint32_t n) {
-  int rc = check_plans(b, plans, n);
-  if (rc) return rc;
-  if (n == 0) return nhp::clear_error();
-  if (!steps) return nhp::set_error(NHP_EINVAL, "steps is NULL");
-  // group the row jobs by section size (one launch each) and collect the x-major jobs
+// One pass for each listed plan, all in shared launches: row jobs grouped by
+// section size and by fused or single (one launch per group), x-major jobs in
+// one more launch.
+static int launch_passes(nhp_batch* b, nhp_plan* const* plans, const nhp::Pass* passes, uint32_t n) {
   static const int kP[4] = {8, 16, 32, 64};
-  std::vector<nhp::SweepJob> group[5];
+  constexpr int kGroups = 9;  // [fused][P], then x-major
+  std::vector<nhp::SweepJob> group[kGroups];
   for (uint32_t k = 0; k < n; k++) {
-    nhp_plan* p = plans[k];
-    if (!p->has_value) return nhp::set_error(NHP_ESTATE, "plans[%u] has no value volume (batch_init first)", k);
-    const int mu = p->p.schedule[steps[k] % p->p.n_schedule];
     nhp::SweepJob row{}, xm{};
-    nhp::make_sweep_jobs(p->d, mu, &row, &xm);
+    if (nhp::make_sweep_jobs(plans[k]->d, passes[k], &row, &xm) < 0)
+      return nhp::set_error(NHP_EINVAL, "section sizes changed while a batch was being formed");
     if (row.blocks) {
       int g = 0;
       while (g < 4 && kP[g] != row.P) g++;
-      if (g == 4) return nhp::set_error(NHP_EINVAL, "plans[%u]: no section size for its curve length", k);
-      group[g].push_back(row);
+      if (g == 4) return nhp::set_error(NHP_EINVAL, "a plan has no section size for its curve length");
+      group[4 * row.fused + g].push_back(row);
     }
-    if (xm.blocks) group[4].push_back(xm);
+    if (xm.blocks) group[8].push_back(xm);
   }
   size_t total_jobs = 0;
   for (auto& g : group) total_jobs += g.size();
   Slot* s;
-  rc = take_slot(b, total_jobs * sizeof(nhp::SweepJob), &s);
+  int rc = take_slot(b, total_jobs * sizeof(nhp::SweepJob), &s);
   if (rc) return rc;
   nhp::SweepJob* h = reinterpret_cast<nhp::SweepJob*>(s->host);
   size_t off = 0;
-  int blocks[5] = {0, 0, 0, 0, 0};
-  size_t first[5];
-  for (int g = 0; g < 5; g++) {
+  int blocks[kGroups] = {};
+  size_t first[kGroups];
+  for (int g = 0; g < kGroups; g++) {
     first[g] = off;
     for (nhp::SweepJob& j : group[g]) {
       j.first_block = blocks[g];
@@ -239,13 +236,56 @@ int batch_step(nhp_batch* b, nhp_plan* const* plans, const uint32_t* steps, uint
   HIP_TRY(hipMemcpyAsync(s->dev, s->host, total_jobs * sizeof(nhp::SweepJob), hipMemcpyHostToDevice, b->stream),
           "job upload");
   const nhp::SweepJob* d = reinterpret_cast<const nhp::SweepJob*>(s->dev);
-  for (int g = 0; g < 5; g++) {
+  for (int g = 0; g < kGroups; g++) {
     if (group[g].empty()) continue;
-    HIP_TRY(nhp::launch_sweep_batch(d + first[g], (int)group[g].size(), blocks[g], g < 4 ? kP[g] : 0, g == 4,
-                                    b->stream),
+    HIP_TRY(nhp::launch_sweep_batch(d + first[g], (int)group[g].size(), blocks[g], g < 8 ? kP[g % 4] : 0,
+                                    g >= 4 && g < 8, g == 8, b->stream),
             "sweep launch");
   }
-  rc = finish_slot(b, s);
+  return finish_slot(b, s);
+}
+
+int batch_advance(nhp_batch* b, nhp_plan* const* plans, const uint32_t* steps, const uint32_t* counts, uint32_t n) {
+  int rc = check_plans(b, plans, n);
+  if (rc) return rc;
+  if (n == 0) return nhp::clear_error();
+  if (!steps || !counts) return nhp::set_error(NHP_EINVAL, "steps or counts is NULL");
+  std::vector<std::vector<nhp::Pass>> passes(n);
+  size_t most = 0;
+  for (uint32_t k = 0; k < n; k++) {
+    nhp_plan* p = plans[k];
+    if (!p->has_value) return nhp::set_error(NHP_ESTATE, "plans[%u] has no value volume (batch_init first)", k);
+    nhp::schedule_passes(p->p.schedule, p->p.n_schedule, steps[k], counts[k], nhp::can_fuse(p->d), passes[k]);
+    most = std::max(most, passes[k].size());
+  }
+  std::vector<nhp_plan*> live;
+  std::vector<nhp::Pass> now;
+  for (size_t t = 0; t < most; t++) {
+    live.clear();
+    now.clear();
+    for (uint32_t k = 0; k < n; k++)
+      if (t < passes[k].size()) {
+        live.push_back(plans[k]);
+        now.push_back(passes[k][t]);
+      }
+    rc = launch_passes(b, live.data(), now.data(), (uint32_t)live.size());
+    if (rc) return rc;
+  }
+  return nhp::clear_error();
+}
+
+int batch_step(nhp_batch* b, nhp_plan* const* plans, const uint32_t* steps, uint32_t n) {
+  int rc = check_plans(b, plans, n);
+  if (rc) return rc;
+  if (n == 0) return nhp::clear_error();
+  if (!steps) return nhp::set_error(NHP_EINVAL, "steps is NULL");
+  std::vector<nhp::Pass> now(n);
+  for (uint32_t k = 0; k < n; k++) {
+    nhp_plan* p = plans[k];
+    if (!p->has_value) return nhp::set_error(NHP_ESTATE, "plans[%u] has no value volume (batch_init first)", k);
+    now[k] = nhp::Pass{(int8_t)p->p.schedule[steps[k] % p->p.n_schedule], (int8_t)-1};
+  }
+  rc = launch_passes(b, plans, now.data(), n);
   return rc ? rc : nhp::clear_error();
 }
 
@@ -257,28 +297,9 @@ int batch_sweep(nhp_batch* b, nhp_plan* const* plans, const uint32_t* starts_ijt
   if (!n_cycles) return nhp::set_error(NHP_EINVAL, "n_cycles is NULL");
   rc = batch_init(b, plans, starts_ijt, n);
   if (rc) return rc;
-  uint32_t max_steps = 0;
-  std::vector<uint32_t> total(n);
-  for (uint32_t k = 0; k < n; k++) {
-    total[k] = n_cycles[k] * plans[k]->p.n_schedule;
-    max_steps = std::max(max_steps, total[k]);
-  }
-  std::vector<nhp_plan*> live;
-  std::vector<uint32_t> step;
-  live.reserve(n);
-  step.reserve(n);
-  for (uint32_t s = 0; s < max_steps; s++) {
-    live.clear();
-    step.clear();
-    for (uint32_t k = 0; k < n; k++)
-      if (s < total[k]) {
-        live.push_back(plans[k]);
-        step.push_back(s);
-      }
-    rc = batch_step(b, live.data(), step.data(), (uint32_t)live.size());
-    if (rc) return rc;
-  }
-  return nhp::clear_error();
+  std::vector<uint32_t> zero(n, 0), total(n);
+  for (uint32_t k = 0; k < n; k++) total[k] = n_cycles[k] * plans[k]->p.n_schedule;
+  return batch_advance(b, plans, zero.data(), total.data(), n);
 }
 
 int batch_extract(nhp_batch* b, nhp_plan* const* plans, uint32_t n, const uint32_t* goals_ijt, const uint32_t* radius,

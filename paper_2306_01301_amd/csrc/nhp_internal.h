@@ -74,7 +74,36 @@ struct SweepJob {
   int tiles_x, blocks, first_block;
   int P;                    // steps per wave (row jobs)
   uint32_t ct, lq;          // transition cost; turn edge length
+  // Turns only: a second maneuver on the same circles in the opposite
+  // direction, applied right after the first while the curves are in
+  // registers (fused = 1); its transition cost and edge length.
+  int fused;
+  uint32_t ct2, lq2;
 };
+
+// A pass over the value volume: one maneuver, or two consecutive turn
+// maneuvers that share their curves (mu2 >= 0).
+struct Pass {
+  int8_t mu, mu2;
+};
+
+// Whether `b` right after `a` can share one pass: both turns on the same
+// circles (left: LF, LB; right: RF, RB) in opposite directions.
+inline bool fusable(int a, int b) {
+  const bool la = a == NHP_LF || a == NHP_LB, lb = b == NHP_LF || b == NHP_LB;
+  const bool ra = a == NHP_RF || a == NHP_RB, rb = b == NHP_RF || b == NHP_RB;
+  return a != b && ((la && lb) || (ra && rb));
+}
+
+// The passes of `count` consecutive sweeps of a schedule starting at step
+// `first` (step k applies schedule[k mod n]); with `pairs`, consecutive
+// fusable sweeps are paired greedily from the first.  Appends to `out`.
+void schedule_passes(const uint8_t* schedule, int n, uint64_t first, uint64_t count, bool pairs,
+                     std::vector<Pass>& out);
+
+// Whether a plan's turn curves fit the fused kernel (at most 32 steps per
+// wave; longer sections leave no registers for the second maneuver).
+bool can_fuse(const DevPlan& d);
 
 struct InitJob {
   uint32_t* V;
@@ -85,8 +114,8 @@ struct InitJob {
 
 int pick_section(int len);
 int set_section_steps(int len, int P);
-int make_sweep_jobs(const DevPlan& d, int mu, SweepJob* row, SweepJob* xmaj);
-hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool xmajor,
+int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj);
+hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool xmajor,
                               hipStream_t s);
 hipError_t launch_init_batch(const InitJob* d_jobs, int n_jobs, size_t max_n4, hipStream_t s);
 
@@ -96,7 +125,7 @@ constexpr int kExStepWords = 9;
 
 hipError_t launch_init(const DevPlan& d, uint32_t start_index, hipStream_t s);
 hipError_t launch_force_walls(const DevPlan& d, hipStream_t s);
-hipError_t launch_sweep(const DevPlan& d, int mu, hipStream_t s);
+hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s);
 hipError_t launch_render(const DevPlan& d, const uint8_t* image, int n_side, int n_len, hipStream_t s);
 hipError_t launch_extract(const DevPlan& d, uint32_t si, uint32_t sj, uint32_t st, uint32_t gi, uint32_t gj,
                           uint32_t gt, int radius, uint32_t w_xy, uint32_t w_t, hipStream_t s);
@@ -122,6 +151,50 @@ struct RenderJob {
 };
 hipError_t launch_render_batch(const RenderJob* d_jobs, int n_jobs, int total_blocks, hipStream_t s);
 
+// ---- maneuver-count reachability (App. C) ----
+// Bit volumes: word ((T * N + j) * W + w), W = N / 32, bit t is pose
+// i = 32 w + t.  A set bit means "not reachable" in a level volume (the
+// paper's inverted convention, so a sweep step is an AND then an OR) and
+// "hard" in the obstacle bit volume.
+constexpr int kReachMaxN = 512;
+constexpr int kReachMaxL = 512;
+constexpr uint32_t kReachMaxCycles = 254;
+constexpr int kReachMaxSteps = 256;
+
+struct ReachDev {
+  int N, L, W;
+  const int32_t* turn_off;  // the plan's [4][L]
+  const int16_t* skew;      // [L][N]
+  const int32_t* family;    // [L]
+  const int32_t* fwd;       // [L]
+  const int32_t* taps;      // [L][2][kMaxTaps]
+  uint32_t* hard;           // obstacle bits, one volume
+  uint32_t* levels;         // level volumes R_0 .. R_max
+  uint32_t* img;            // [N][W] image bits (rendering scratch)
+  uint32_t* extract;        // header + steps
+  size_t vol_words;         // N * N * L / 32
+};
+
+hipError_t launch_reach_render(const ReachDev& r, const uint8_t* image, int n_side, int n_len, hipStream_t s);
+hipError_t launch_reach_pack(const ReachDev& r, const uint8_t* codes, hipStream_t s);
+hipError_t launch_reach_start(const ReachDev& r, uint32_t start_index, hipStream_t s);
+// One cycle: R_{m+1} from R_m with the scheduled maneuvers (at most three
+// launches: left circles, right circles, straight planes).
+hipError_t launch_reach_cycle(const ReachDev& r, const uint8_t* schedule, int n_schedule, uint32_t m, hipStream_t s);
+
+struct ReachExArgs {
+  DevPlan d;  // tables for the curve geometry (predecessors)
+  const uint32_t* hard;
+  const uint32_t* levels;
+  size_t vol_words;
+  int W;
+  int n_levels;  // level volumes computed (cycles + 1)
+  uint32_t gi, gj, gt;
+  int radius;
+  uint32_t* out;
+};
+hipError_t launch_reach_extract(const ReachExArgs& x, hipStream_t s);
+
 }  // namespace nhp
 
 // The plan object behind the opaque handle of the C ABI.
@@ -138,8 +211,11 @@ struct nhp_plan {
   bool has_value = false;
   uint32_t start[3] = {0, 0, 0};
   int front = -1, rear = -1, half_width = -1;  // box of the last render (sample offsets cached)
-  hipGraphExec_t cycle = nullptr;  // one cycle of the schedule, captured once, replayed per cycle
-  bool graph_failed = false;       // capture unavailable: launch the kernels directly
+  // One cycle of the schedule, captured once and replayed per cycle; indexed
+  // by [first sweep already done by the previous cycle's last pass][last
+  // sweep may pair with the next cycle's first].
+  hipGraphExec_t cycle[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  bool graph_failed = false;  // capture unavailable: launch the kernels directly
 };
 
 namespace nhp {

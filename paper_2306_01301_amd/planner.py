@@ -68,17 +68,29 @@ SIGNATURES = {
     "sweep_n_turns": (ctypes.c_int, [_vp, _u32, _u32, _u32, _u32]),
     "sweep_resume": (ctypes.c_int, [_vp, _u32]),
     "sweep_one": (ctypes.c_int, [_vp, _u32]),
+    "sweep_pass": (ctypes.c_int, [_vp, _i32, _i32]),
+    "schedule_passes": (ctypes.c_int, [_vp, _u32, ctypes.c_uint64, ctypes.c_uint64, _i32, _vp, _vp, _u32, _PU32]),
     "extract_path": (ctypes.c_int, [_vp, _u32, _u32, _u32, _u32, _u32, _u32, ctypes.POINTER(NhpStep), _u32,
                                     _PU32, _PU32, _PU32, _PU32]),
     "plan_device_ptrs": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "plan_get_tables": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "plan_last_error": (ctypes.c_char_p, []),
     "nhp_set_section_steps": (ctypes.c_int, [_u32, _u32]),
+    "reach_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(NhpParams), _u32]),
+    "reach_create": (ctypes.c_int, [_vp, _u32, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    "reach_destroy": (ctypes.c_int, [_vp]),
+    "reach_render": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32]),
+    "reach_set_cspace": (ctypes.c_int, [_vp, _vp]),
+    "reach_sweep": (ctypes.c_int, [_vp, _u32, _u32, _u32, _u32]),
+    "reach_extract": (ctypes.c_int, [_vp, _u32, _u32, _u32, _u32, ctypes.POINTER(NhpStep), _u32, _PU32, _PU32,
+                                     _PU32]),
+    "reach_device_ptrs": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "batch_create": (ctypes.c_int, [_u32, _vp, ctypes.POINTER(_vp)]),
     "batch_destroy": (ctypes.c_int, [_vp]),
     "batch_render": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
     "batch_init": (ctypes.c_int, [_vp, _vp, _vp, _u32]),
     "batch_step": (ctypes.c_int, [_vp, _vp, _vp, _u32]),
+    "batch_advance": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
     "batch_sweep": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
     "batch_extract": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp, _vp, ctypes.POINTER(NhpStep), _u32, _vp, _vp,
                                      _vp, _vp, _vp]),
@@ -121,6 +133,18 @@ def apply_tuning(path: str = TUNING_PATH) -> dict:
 
 def set_section_steps(curve_len: int, steps: int) -> None:
     _check(lib().nhp_set_section_steps(int(curve_len), int(steps)), "nhp_set_section_steps")
+
+
+def schedule_passes(schedule: Sequence[int], first_step: int, n_steps: int, pairs: bool = True):
+    """The passes (first, second or -1) that the library groups sweeps
+    first_step .. first_step + n_steps - 1 of a schedule into."""
+    sched = (ctypes.c_uint8 * len(schedule))(*schedule)
+    n = ctypes.c_uint32()
+    cap = max(1, int(n_steps))
+    a, b = (ctypes.c_int8 * cap)(), (ctypes.c_int8 * cap)()
+    _check(lib().schedule_passes(sched, len(schedule), int(first_step), int(n_steps), int(bool(pairs)), a, b, cap,
+                                 ctypes.byref(n)), "schedule_passes")
+    return [(int(a[k]), int(b[k])) for k in range(n.value)]
 
 
 class NhpError(RuntimeError):
@@ -245,6 +269,10 @@ class Planner:
     def sweep_one(self, maneuver: int) -> None:
         _check(lib().sweep_one(self._plan, int(maneuver)), "sweep_one")
 
+    def sweep_pass(self, first: int, second: int = -1) -> None:
+        """`first` then `second` (-1: none), in one pass when they fuse."""
+        _check(lib().sweep_pass(self._plan, int(first), int(second)), "sweep_pass")
+
     def extract(self, goal: Sequence[int], radius: int = 0, w_xy: int = 1024, w_t: int = 1024,
                 cap: int = MAX_STEPS_DEVICE) -> Path:
         steps = (NhpStep * max(1, cap))()
@@ -334,6 +362,13 @@ class Batch:
         s = _u32array(steps)
         _check(lib().batch_step(self._b, self._handles(planners), s.ctypes.data, len(planners)), "batch_step")
 
+    def advance(self, planners, steps, counts) -> None:
+        """Plan k runs sweeps steps[k] .. steps[k] + counts[k] - 1 (fusing
+        consecutive turns on shared circles)."""
+        s, c = _u32array(steps), _u32array(counts)
+        _check(lib().batch_advance(self._b, self._handles(planners), s.ctypes.data, c.ctypes.data, len(planners)),
+               "batch_advance")
+
     def sweep(self, planners, starts, n_cycles) -> None:
         s, n = _u32array(starts), _u32array(n_cycles)
         _check(lib().batch_sweep(self._b, self._handles(planners), s.ctypes.data, n.ctypes.data, len(planners)),
@@ -374,3 +409,92 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+@dataclass
+class ReachPath:
+    steps: List[Step]
+    best: Tuple[int, int, int]
+    level: int  # maneuvers used
+
+
+class Reach:
+    """Maneuver-count reachability (App. C) on a planner's tables and
+    stream: obstacle bits and level bit volumes in a workspace tensor."""
+
+    def __init__(self, planner: Planner, max_cycles: int, workspace: Optional[torch.Tensor] = None):
+        L = lib()
+        self.planner = planner
+        self.max_cycles = int(max_cycles)
+        nbytes = int(L.reach_workspace_bytes(ctypes.byref(planner.params), self.max_cycles))
+        if nbytes == 0:
+            raise NhpError(EINVAL, "reach_workspace_bytes")
+        if workspace is None:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=planner.device)
+        off = (-workspace.data_ptr()) % 256
+        self.ws = workspace[off:off + nbytes]
+        self._r = ctypes.c_void_p()
+        with torch.cuda.device(planner.device):
+            _check(L.reach_create(planner._plan, self.max_cycles, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                  ctypes.byref(self._r)), "reach_create")
+        h, v = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(L.reach_device_ptrs(self._r, ctypes.byref(h), ctypes.byref(v)), "reach_device_ptrs")
+        base = self.ws.data_ptr()
+        self._h_off, self._l_off = h.value - base, v.value - base
+        self.words = planner.n_poses // 32
+
+    def hard_words(self) -> torch.Tensor:
+        return self.ws[self._h_off:self._h_off + 4 * self.words].view(torch.int32)
+
+    def level_words(self, m: int) -> torch.Tensor:
+        o = self._l_off + 4 * self.words * int(m)
+        return self.ws[o:o + 4 * self.words].view(torch.int32)
+
+    def render(self, image: torch.Tensor, vehicle: Sequence[int]) -> None:
+        assert image.dtype == torch.uint8 and image.is_cuda and image.shape == (self.planner.nx, self.planner.nx)
+        image = image.contiguous()
+        self._image = image
+        f, r, s = (int(v) for v in vehicle)
+        _check(lib().reach_render(self._r, ctypes.c_void_p(image.data_ptr()), f, r, s), "reach_render")
+
+    def set_cspace(self, codes: torch.Tensor) -> None:
+        assert codes.dtype == torch.uint8 and codes.is_cuda and codes.numel() == self.planner.n_poses
+        codes = codes.contiguous()
+        self._codes = codes
+        _check(lib().reach_set_cspace(self._r, ctypes.c_void_p(codes.data_ptr())), "reach_set_cspace")
+
+    def sweep(self, start: Sequence[int], n_cycles: int) -> None:
+        i, j, t = (int(v) for v in start)
+        _check(lib().reach_sweep(self._r, i, j, t, int(n_cycles)), "reach_sweep")
+
+    def extract(self, goal: Sequence[int], radius: int = 0, cap: int = 256) -> ReachPath:
+        steps = (NhpStep * max(1, cap))()
+        n, best, lv = ctypes.c_uint32(), (ctypes.c_uint32 * 3)(), ctypes.c_uint32()
+        gi, gj, gt = (int(v) for v in goal)
+        _check(lib().reach_extract(self._r, gi, gj, gt, int(radius), steps, int(cap), ctypes.byref(n), best,
+                                   ctypes.byref(lv)), "reach_extract")
+        out = [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_ijt),
+                    tuple(int(v) for v in s.to_ijt), int(s.cost_q10)) for s in steps[: n.value]]
+        return ReachPath(out, tuple(int(v) for v in best), int(lv.value))
+
+    def close(self) -> None:
+        if getattr(self, "_r", None) is not None and self._r.value:
+            self.planner.stream.synchronize()
+            lib().reach_destroy(self._r)
+            self._r = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bits_to_levels(words: Sequence[np.ndarray], shape) -> np.ndarray:
+    """Per-pose level (smallest m whose volume has the pose's bit clear, 255
+    if none) from level volumes given as uint32 word arrays."""
+    level = np.full(int(np.prod(shape)), 255, np.uint8)
+    for m, w in enumerate(words):
+        bits = np.unpackbits(np.asarray(w, np.uint32).view(np.uint8), bitorder="little").astype(bool)
+        level[(~bits) & (level == 255)] = m
+    return level.reshape(shape)

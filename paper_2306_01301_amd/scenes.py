@@ -301,8 +301,26 @@ def random_small(seed: int, n: int = 32, nt: int = 32, R: float = 4.0, n_cycles:
                  gear=tuple(gear), schedule=tuple(schedule), half_cell=half_cell, seed=seed)
 
 
+def reach_128(seed: int = 1307) -> Scene:
+    """Maneuver-count reachability workload of App. C's timing table: 128 x
+    128 cells x 512 headings, N = 8 maneuver cycles, hard obstacles only
+    (axis-aligned rectangles, about 10 % of the area), vehicle 6 x 3, R = 10.
+    The goal lies 3 cells along x and 24 against y from the start, turned
+    by 180 degrees, like the example the paper solves with four maneuvers."""
+    rng = np.random.default_rng(seed)
+    n, nt = 128, 512
+    veh = vehicle_box(6, 3)
+    start, goal = (60, 80, 0), (63, 56, 256)
+    img = rect_clutter(rng, n, 24, 4, 14)
+    for (i, j, _t) in (start, goal):  # keep the end poses clear
+        img[max(0, j - 8): j + 9, max(0, i - 8): i + 9] = 0
+    return Scene("reach_128", n, nt, 10.0, img, veh, start, goal, n_cycles=8, ct=uniform_ct(10), half_cell=1,
+                 goal_radius=0, seed=seed)
+
+
 WORKLOADS = {
     "plain_64": plain_64,
     "parking_256": parking_256,
     "maze_512": maze_512,
+    "reach_128": reach_128,
 }

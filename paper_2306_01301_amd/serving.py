@@ -8,8 +8,8 @@ continuous-batching server.
 * `Server`: requests arrive over time (e.g. Poisson); a request is admitted
   when its HBM footprint fits the budget, its map and volumes then stay on
   the device until it completes.  Every tick advances every admitted plan by
-  a number of sweeps inversely proportional to its size (one batch_step call
-  per sub-step, all live plans in shared launches); plans that finish their
+  a number of sweeps inversely proportional to its size (one batch_advance
+  call, all live plans in shared launches); plans that finish their
   sweeps are extracted together and release their memory, and requests that
   arrived meanwhile are admitted at the next tick.
 
@@ -171,9 +171,7 @@ class Server:
             biggest = max(l.scene.n_poses for l in live)
             for l in live:
                 l.per_tick = max(1, min(l.total - l.done, int(round(biggest / l.scene.n_poses))))
-            for sub in range(max(l.per_tick for l in live)):
-                cur = [l for l in live if sub < l.per_tick]
-                self.batch.step([l.planner for l in cur], [l.done + sub for l in cur])
+            self.batch.advance([l.planner for l in live], [l.done for l in live], [l.per_tick for l in live])
             for l in live:
                 l.done += l.per_tick
             finished = [l for l in live if l.done >= l.total]

@@ -1,0 +1,147 @@
+"""GPU parity of fused turn passes: two consecutive turn maneuvers on the
+same circles in opposite directions (RB then RF, LB then LF, either order,
+also across a cycle boundary) run as one pass over the volume.  Every
+schedule and section size gives exactly the oracle's values, which applies
+the maneuvers one at a time (Insert 1, Sec. VIII.B)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2306_01301_amd import planner as P
+from paper_2306_01301_amd import scenes
+from tests.common import problem_of
+
+pytestmark = pytest.mark.gpu
+
+INF = 0xFFFFFFFF
+LF, SF, RB, RF, SB, LB = range(6)
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.lib()
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _random_values(rng, shape):
+    V = rng.integers(0, 1 << 24, size=shape, dtype=np.uint64).astype(np.uint32)
+    V[rng.random(shape) < 0.3] = INF
+    near = rng.random(shape) < 0.02
+    V[near] = (INF - rng.integers(1, 1 << 16, size=int(near.sum()))).astype(np.uint32)
+    return V
+
+
+SCHEDULES = [
+    (RB, RF),
+    (RF, RB),
+    (LB, LF),
+    (LF, LB),
+    (LB, SF, LF),        # the pair closes across the cycle boundary
+    (RF, LB, LF, RB),    # one pair inside, one across
+    (LF, LB, LF),        # a pair, then a turn with no partner
+    scenes.DEFAULT_SCHEDULE,
+]
+
+
+@pytest.mark.parametrize("N,L,R,steps", [(64, 64, 8.0, 0), (96, 40, 5.0, 16), (136, 72, 6.0, 8),
+                                         (200, 128, 9.0, 32), (96, 256, 12.0, 16)])
+def test_fused_cycles_match_oracle_on_random_values(N, L, R, steps):
+    rng = np.random.default_rng(N * 7 + L)
+    base = scenes.random_small(int(rng.integers(1 << 30)), n=N, nt=L, R=R, n_rect=max(2, N // 8))
+    if steps:
+        P.set_section_steps(L, steps)
+    try:
+        for sched in SCHEDULES:
+            sc = base.with_(schedule=tuple(sched))
+            prob = problem_of(sc)
+            B = oracle.render(prob, sc.image, *sc.vehicle)
+            p = P.planner_for(sc)
+            p.set_cspace(_dev(B))
+            p.sweep(sc.start, 0)
+            for n_cycles in (1, 3):
+                note("fused %s schedule=%s n=%d" % ((N, L, R, steps), [oracle.NAMES[m] for m in sched], n_cycles))
+                V = _random_values(rng, B.shape)
+                p.value.copy_(_dev(V.view(np.int32)))
+                p.resume(n_cycles)
+                got = p.value_numpy()
+                oracle.cycles(prob, B, V, n_cycles)
+                bad = np.argwhere(got != V)
+                assert bad.size == 0, (sched, n_cycles, bad[:5])
+            p.close()
+    finally:
+        if steps:
+            P.set_section_steps(L, 0)
+            P.apply_tuning()
+
+
+def test_graph_variants_replay_consistently():
+    """Cycles come from up to four captured graphs (first sweep already done
+    or not, last sweep paired with the next cycle or not); repeated runs of
+    different lengths on one plan, with eager work in between, give the
+    oracle's values every time."""
+    sc = scenes.random_small(77, n=96, nt=48, R=6.0, n_cycles=3)
+    prob = problem_of(sc)
+    B = oracle.render(prob, sc.image, *sc.vehicle)
+    p = P.planner_for(sc)
+    p.set_cspace(_dev(B))
+    for n_cycles in (2, 4, 1, 3, 4, 2):
+        note("graph variants n=%d" % n_cycles)
+        p.sweep(sc.start, n_cycles)
+        got = p.value_numpy()
+        p.sweep_one(LF)  # eager work between replays
+        torch.cuda.synchronize()
+        V = oracle.init(prob, B, sc.start)
+        oracle.cycles(prob, B, V, n_cycles)
+        assert np.array_equal(got, V), n_cycles
+    p.close()
+
+
+def test_batch_advance_matches_sweeps_one_at_a_time():
+    """Plans at different points of their schedules advanced by different
+    numbers of sweeps in shared launches equal the oracle's maneuvers applied
+    one at a time."""
+    rng = np.random.default_rng(2024)
+    scs = [
+        scenes.random_small(201, n=64, nt=64, R=8.0),
+        scenes.random_small(202, n=96, nt=48, R=6.0, schedule=(LB, SF, LF)),
+        scenes.random_small(203, n=40, nt=24, R=3.0, schedule=(RF, LB, LF, RB)),
+        scenes.random_small(204, n=128, nt=128, R=12.0),
+        scenes.random_small(205, n=72, nt=40, R=5.0, schedule=scenes.FORWARD_SCHEDULE),
+    ]
+    probs = [problem_of(sc) for sc in scs]
+    Bs = [oracle.render(pr, sc.image, *sc.vehicle) for pr, sc in zip(probs, scs)]
+    planners = [P.planner_for(sc) for sc in scs]
+    batch = P.Batch(len(scs))
+    for p, B in zip(planners, Bs):
+        p.set_cspace(_dev(B))
+    batch.init(planners, [sc.start for sc in scs])
+    for rnd in range(3):
+        Vs = [_random_values(rng, B.shape) for B in Bs]
+        for p, V in zip(planners, Vs):
+            p.value.copy_(_dev(V.view(np.int32)))
+        steps = [int(rng.integers(0, 12)) for _ in scs]
+        counts = [int(rng.integers(0, 9)) for _ in scs]
+        note("batch_advance round %d steps=%s counts=%s" % (rnd, steps, counts))
+        batch.advance(planners, steps, counts)
+        for k, (sc, pr, B, V) in enumerate(zip(scs, probs, Bs, Vs)):
+            for s in range(steps[k], steps[k] + counts[k]):
+                oracle.sweep(pr, sc.schedule[s % len(sc.schedule)], B, V)
+            assert np.array_equal(planners[k].value_numpy(), V), (rnd, k)
+    batch.close()
+    for p in planners:
+        p.close()
