@@ -100,6 +100,99 @@ struct RowShared {
   uint16_t shift[1024];    // per step: column offset of curve x' (reduced mod N)
 };
 
+// The scan phases of one section held in registers, then its stores.
+// GUARD: the curve length is not a multiple of P, so the last section has
+// fewer than P real steps and the steps past the curve are skipped (without
+// it every section is full and the loops carry no conditions).
+template <int P, bool FUSED, bool GUARD>
+__device__ __forceinline__ void scan_section(const SweepJob& a, RowShared& sh, uint32_t (&u)[P], uint32_t (&code)[P],
+                                             int n_real, int S, int wave, int lane, bool cyclic, bool busy,
+                                             bool active, int xp, int first, int N) {
+  uint32_t packed[FUSED ? P / 4 : 1];
+  if (busy) {
+    // weights replace the codes; compose the section into (D, C):
+    // min(C + w, u + ct + w) = min(C, u + ct) + w (saturating add is monotone).
+    // A fused pair keeps the codes, packed four to a register, for the
+    // second maneuver's weights (packing after the loads have landed, so it
+    // does not hold the loads back).
+    uint32_t D = 0, C = kInf;
+    if (FUSED) {
+#pragma unroll
+      for (int q = 0; q < P / 4; q++)
+        packed[q] = code[4 * q] | (code[4 * q + 1] << 8) | (code[4 * q + 2] << 16) | (code[4 * q + 3] << 24);
+    }
+#pragma unroll
+    for (int k = 0; k < P; k++) code[k] = sh.wlut[code[k]];
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+      if (!GUARD || k < n_real) {
+        C = sadd(umin(C, sadd(u[k], a.ct)), code[k]);
+        D = sadd(D, code[k]);
+      }
+    }
+    sh.aggD[wave][lane] = D;
+    sh.aggC[wave][lane] = C;
+  }
+  __syncthreads();
+  if (busy) {
+    uint32_t v = section_carry(sh.aggD, sh.aggC, S, wave, lane, cyclic);
+    // replay: a hard pose has weight INF, and w >> 31 (arithmetic) is then
+    // all ones, which forces its output to INF
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+      const uint32_t w = code[k];
+      const uint32_t uu = u[k];
+      u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+      v = sadd(umin(v, sadd(uu, a.ct)), w);
+    }
+    if (FUSED) {
+      // second maneuver: the steps of the section in reverse order, its
+      // weights replacing the codes
+      uint32_t D2 = 0, C2 = kInf;
+#pragma unroll
+      for (int k = P - 1; k >= 0; k--) {
+        if (!GUARD || k < n_real) {
+          code[k] = sh.wlut2[(packed[k >> 2] >> (8 * (k & 3))) & 0xffu];
+          C2 = sadd(umin(C2, sadd(u[k], a.ct2)), code[k]);
+          D2 = sadd(D2, code[k]);
+        }
+      }
+      sh.aggD2[wave][lane] = D2;
+      sh.aggC2[wave][lane] = C2;
+    }
+  }
+  if (FUSED) {
+    __syncthreads();
+    if (busy) {
+      uint32_t v = section_carry<true>(sh.aggD2, sh.aggC2, S, wave, lane, cyclic);
+#pragma unroll
+      for (int k = P - 1; k >= 0; k--) {
+        if (!GUARD || k < n_real) {
+          const uint32_t w = code[k];
+          const uint32_t uu = u[k];
+          u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+          v = sadd(umin(v, sadd(uu, a.ct2)), w);
+        }
+      }
+    }
+  }
+  if (busy) {
+    // recompute the column of every step rather than keeping P of them live
+    int xs = xp;
+    asm volatile("" : "+v"(xs));
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < P; k++) {
+        if (!GUARD || k < n_real) {
+          int i = xs + (int)sh.shift[first + k];
+          i -= (i >= N) ? N : 0;
+          st_value(a.V, sh.row_base[first + k] + (uint32_t)i, u[k]);
+        }
+      }
+    }
+  }
+}
+
 // Row-coalesced sweep of one tile (64 curves) of a job: turns (cyclic) and
 // y-major straights.
 //   turns:     tile -> (x tile, y'); step k -> plane T_k, offsets (ox, oy)
@@ -107,7 +200,7 @@ struct RowShared {
 // FUSED (turns): after the first maneuver the second one, on the same curves
 // in the opposite direction, runs on the values still held in registers, so
 // the pair costs one read and one write per pose.
-template <int P, bool FUSED>
+template <int P, bool FUSED, bool GUARD>
 __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowShared& sh) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -158,7 +251,6 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
 
   uint32_t u[P];
   uint32_t code[P];
-  uint32_t packed[FUSED ? P / 4 : 1];
   // Sections are P steps; steps past the curve length (when S P > L) are
   // identity maps that touch no memory.
   const int n_real = (L - wave * P) < P ? (L - wave * P) : P;  // real steps of this wave
@@ -179,88 +271,7 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
       code[k] = a.B[cell];
     }
   }
-  if (busy) {
-    // weights replace the codes; compose the section into (D, C):
-    // min(C + w, u + ct + w) = min(C, u + ct) + w (saturating add is monotone).
-    // A fused pair keeps the codes, packed four to a register, for the
-    // second maneuver's weights (packing after the loads have landed, so it
-    // does not hold the loads back).
-    uint32_t D = 0, C = kInf;
-    if (FUSED) {
-#pragma unroll
-      for (int q = 0; q < P / 4; q++)
-        packed[q] = code[4 * q] | (code[4 * q + 1] << 8) | (code[4 * q + 2] << 16) | (code[4 * q + 3] << 24);
-    }
-#pragma unroll
-    for (int k = 0; k < P; k++) code[k] = sh.wlut[code[k]];
-#pragma unroll
-    for (int k = 0; k < P; k++) {
-      if (k < n_real) {
-        C = sadd(umin(C, sadd(u[k], a.ct)), code[k]);
-        D = sadd(D, code[k]);
-      }
-    }
-    sh.aggD[wave][lane] = D;
-    sh.aggC[wave][lane] = C;
-  }
-  __syncthreads();
-  if (busy) {
-    uint32_t v = section_carry(sh.aggD, sh.aggC, S, wave, lane, cyclic);
-    // replay: a hard pose has weight INF, and w >> 31 (arithmetic) is then
-    // all ones, which forces its output to INF
-#pragma unroll
-    for (int k = 0; k < P; k++) {
-      const uint32_t w = code[k];
-      const uint32_t uu = u[k];
-      u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
-      v = sadd(umin(v, sadd(uu, a.ct)), w);
-    }
-    if (FUSED) {
-      // second maneuver: the steps of the section in reverse order, its
-      // weights replacing the codes
-      uint32_t D2 = 0, C2 = kInf;
-#pragma unroll
-      for (int k = P - 1; k >= 0; k--) {
-        if (k < n_real) {
-          code[k] = sh.wlut2[(packed[k >> 2] >> (8 * (k & 3))) & 0xffu];
-          C2 = sadd(umin(C2, sadd(u[k], a.ct2)), code[k]);
-          D2 = sadd(D2, code[k]);
-        }
-      }
-      sh.aggD2[wave][lane] = D2;
-      sh.aggC2[wave][lane] = C2;
-    }
-  }
-  if (FUSED) {
-    __syncthreads();
-    if (busy) {
-      uint32_t v = section_carry<true>(sh.aggD2, sh.aggC2, S, wave, lane, cyclic);
-#pragma unroll
-      for (int k = P - 1; k >= 0; k--) {
-        if (k < n_real) {
-          const uint32_t w = code[k];
-          const uint32_t uu = u[k];
-          u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
-          v = sadd(umin(v, sadd(uu, a.ct2)), w);
-        }
-      }
-    }
-  }
-  if (busy) {
-    // recompute the column of every step rather than keeping P of them live
-    int xs = xp;
-    asm volatile("" : "+v"(xs));
-    if (active) {
-#pragma unroll
-      for (int k = 0; k < P; k++) {
-        if (k < n_real) {
-          int i = xs + (int)sh.shift[first + k];
-          i -= (i >= N) ? N : 0;
-          st_value(a.V, sh.row_base[first + k] + (uint32_t)i, u[k]);
-        }
-      }
-    }
-  }
+  scan_section<P, FUSED, GUARD>(a, sh, u, code, n_real, S, wave, lane, cyclic, busy, active, xp, first, N);
 }
 
 // x-major straights (|tan| <= 1): line x' visits (c, x' + B(c)), so lines
@@ -411,19 +422,19 @@ __device__ __forceinline__ int find_job(const SweepJob* __restrict__ jobs, int n
   return lo;
 }
 
-template <int P, bool FUSED>
+template <int P, bool FUSED, bool GUARD>
 __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepJob job) {
   __shared__ RowShared sh;
-  row_sweep_tile<P, FUSED>(job, xcd_tile(blockIdx.x, gridDim.x), sh);
+  row_sweep_tile<P, FUSED, GUARD>(job, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
 
-template <int P, bool FUSED>
+template <int P, bool FUSED, bool GUARD>
 __global__ __launch_bounds__(1024) void row_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs) {
   __shared__ RowShared sh;
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
   const SweepJob job = jobs[j];
-  row_sweep_tile<P, FUSED>(job, t - job.first_block, sh);
+  row_sweep_tile<P, FUSED, GUARD>(job, t - job.first_block, sh);
 }
 
 template <int Q>
@@ -594,24 +605,26 @@ int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj) 
   return n;
 }
 
-template <bool FUSED>
+template <bool FUSED, bool GUARD>
 hipError_t launch_row_job_t(const SweepJob& j, hipStream_t s) {
   const dim3 grid(j.blocks), block(64 * ((j.L + j.P - 1) / j.P));
   switch (j.P) {
     case 64:
       if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
-      hipLaunchKernelGGL((row_sweep_kernel<64, false>), grid, block, 0, s, j);
+      hipLaunchKernelGGL((row_sweep_kernel<64, false, GUARD>), grid, block, 0, s, j);
       break;
-    case 32: hipLaunchKernelGGL((row_sweep_kernel<32, FUSED>), grid, block, 0, s, j); break;
-    case 16: hipLaunchKernelGGL((row_sweep_kernel<16, FUSED>), grid, block, 0, s, j); break;
-    case 8: hipLaunchKernelGGL((row_sweep_kernel<8, FUSED>), grid, block, 0, s, j); break;
+    case 32: hipLaunchKernelGGL((row_sweep_kernel<32, FUSED, GUARD>), grid, block, 0, s, j); break;
+    case 16: hipLaunchKernelGGL((row_sweep_kernel<16, FUSED, GUARD>), grid, block, 0, s, j); break;
+    case 8: hipLaunchKernelGGL((row_sweep_kernel<8, FUSED, GUARD>), grid, block, 0, s, j); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_row_job(const SweepJob& j, hipStream_t s) {
-  return j.fused ? launch_row_job_t<true>(j, s) : launch_row_job_t<false>(j, s);
+  const bool guard = j.L % j.P != 0;
+  if (j.fused) return guard ? launch_row_job_t<true, true>(j, s) : launch_row_job_t<true, false>(j, s);
+  return guard ? launch_row_job_t<false, true>(j, s) : launch_row_job_t<false, false>(j, s);
 }
 
 hipError_t launch_init(const DevPlan& d, uint32_t start_index, hipStream_t s) {
@@ -654,31 +667,34 @@ hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s) {
   return hipSuccess;
 }
 
-template <bool FUSED>
+template <bool FUSED, bool GUARD>
 hipError_t launch_row_batch_t(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, hipStream_t s) {
   const dim3 grid(total_blocks), block(1024);
   switch (P) {
     case 64:
       if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
-      hipLaunchKernelGGL((row_sweep_batch_kernel<64, false>), grid, block, 0, s, d_jobs, n_jobs);
+      hipLaunchKernelGGL((row_sweep_batch_kernel<64, false, GUARD>), grid, block, 0, s, d_jobs, n_jobs);
       break;
-    case 32: hipLaunchKernelGGL((row_sweep_batch_kernel<32, FUSED>), grid, block, 0, s, d_jobs, n_jobs); break;
-    case 16: hipLaunchKernelGGL((row_sweep_batch_kernel<16, FUSED>), grid, block, 0, s, d_jobs, n_jobs); break;
-    case 8: hipLaunchKernelGGL((row_sweep_batch_kernel<8, FUSED>), grid, block, 0, s, d_jobs, n_jobs); break;
+    case 32: hipLaunchKernelGGL((row_sweep_batch_kernel<32, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs); break;
+    case 16: hipLaunchKernelGGL((row_sweep_batch_kernel<16, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs); break;
+    case 8: hipLaunchKernelGGL((row_sweep_batch_kernel<8, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool xmajor,
-                              hipStream_t s) {
+hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool guard,
+                              bool xmajor, hipStream_t s) {
   if (n_jobs == 0) return hipSuccess;
   if (xmajor) {
     hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ>), dim3(total_blocks), dim3(256), 0, s, d_jobs, n_jobs);
     return hipGetLastError();
   }
-  return fused ? launch_row_batch_t<true>(d_jobs, n_jobs, total_blocks, P, s)
-               : launch_row_batch_t<false>(d_jobs, n_jobs, total_blocks, P, s);
+  if (fused)
+    return guard ? launch_row_batch_t<true, true>(d_jobs, n_jobs, total_blocks, P, s)
+                 : launch_row_batch_t<true, false>(d_jobs, n_jobs, total_blocks, P, s);
+  return guard ? launch_row_batch_t<false, true>(d_jobs, n_jobs, total_blocks, P, s)
+               : launch_row_batch_t<false, false>(d_jobs, n_jobs, total_blocks, P, s);
 }
 
 }  // namespace nhp

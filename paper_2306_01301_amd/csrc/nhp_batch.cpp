@@ -202,7 +202,7 @@ int batch_init(nhp_batch* b, nhp_plan* const* plans, const uint32_t* starts_ijt,
 // one more launch.
 static int launch_passes(nhp_batch* b, nhp_plan* const* plans, const nhp::Pass* passes, uint32_t n) {
   static const int kP[4] = {8, 16, 32, 64};
-  constexpr int kGroups = 9;  // [fused][P], then x-major
+  constexpr int kRow = 16, kGroups = kRow + 1;  // [guard][fused][P], then x-major
   std::vector<nhp::SweepJob> group[kGroups];
   for (uint32_t k = 0; k < n; k++) {
     nhp::SweepJob row{}, xm{};
@@ -212,9 +212,9 @@ static int launch_passes(nhp_batch* b, nhp_plan* const* plans, const nhp::Pass* 
       int g = 0;
       while (g < 4 && kP[g] != row.P) g++;
       if (g == 4) return nhp::set_error(NHP_EINVAL, "a plan has no section size for its curve length");
-      group[4 * row.fused + g].push_back(row);
+      group[8 * (row.L % row.P != 0) + 4 * row.fused + g].push_back(row);
     }
-    if (xm.blocks) group[8].push_back(xm);
+    if (xm.blocks) group[kRow].push_back(xm);
   }
   size_t total_jobs = 0;
   for (auto& g : group) total_jobs += g.size();
@@ -238,8 +238,8 @@ static int launch_passes(nhp_batch* b, nhp_plan* const* plans, const nhp::Pass* 
   const nhp::SweepJob* d = reinterpret_cast<const nhp::SweepJob*>(s->dev);
   for (int g = 0; g < kGroups; g++) {
     if (group[g].empty()) continue;
-    HIP_TRY(nhp::launch_sweep_batch(d + first[g], (int)group[g].size(), blocks[g], g < 8 ? kP[g % 4] : 0,
-                                    g >= 4 && g < 8, g == 8, b->stream),
+    HIP_TRY(nhp::launch_sweep_batch(d + first[g], (int)group[g].size(), blocks[g], g < kRow ? kP[g % 4] : 0,
+                                    g < kRow && (g & 4), g < kRow && (g & 8), g == kRow, b->stream),
             "sweep launch");
   }
   return finish_slot(b, s);

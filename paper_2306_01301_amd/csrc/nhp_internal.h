@@ -115,8 +115,9 @@ struct InitJob {
 int pick_section(int len);
 int set_section_steps(int len, int P);
 int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj);
-hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool xmajor,
-                              hipStream_t s);
+// Row jobs of one launch share P, fused and guard (= L % P != 0).
+hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool guard,
+                              bool xmajor, hipStream_t s);
 hipError_t launch_init_batch(const InitJob* d_jobs, int n_jobs, size_t max_n4, hipStream_t s);
 
 // extract buffer layout (uint32 words)
