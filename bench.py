@@ -37,9 +37,9 @@ BYTES_PER_UPDATE = 9  # read V (4 B) + read obstacle code (1 B) + write V (4 B),
 TURNS = (0, 2, 3, 5)   # LF, RB, RF, LB
 # pass kinds: the kernels one pass of each kind launches
 PASS_KINDS = {
-    "fused_turn": "row_sweep_kernel<32, true> (two turn maneuvers on shared circles in one pass)",
-    "turn": "row_sweep_kernel<32, false> (one turn maneuver)",
-    "straight": "row_sweep_kernel<32, false> (y-major planes) + xmajor_sweep_kernel<32> (x-major planes)",
+    "fused_turn": "row_sweep_kernel<32, true, false> (two turn maneuvers on shared circles in one pass)",
+    "turn": "row_sweep_kernel<32, false, false> (one turn maneuver)",
+    "straight": "row_sweep_kernel<32, false, false> (y-major planes) + xmajor_sweep_kernel<32, 256> (x-major planes)",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweeps_maze_512.json")
 
@@ -356,7 +356,9 @@ def main() -> int:
                            "ms_per_step": float(np.sum(v)) / args.steps,
                            "GB_per_s": alg_bytes / (avg * 1e-3) / 1e9,
                            "updates_per_pose": 2 if k == "fused_turn" else 1, "kernel": PASS_KINDS[k]}
-    dom = max(per_kind, key=lambda k: per_kind[k]["ms_per_step"])
+    # the dominant kernel: a straight pass is two kernels (y-major and x-major
+    # planes), each with a smaller share than a pass kind of one kernel
+    dom = max((k for k in per_kind if k != "straight"), key=lambda k: per_kind[k]["ms_per_step"])
     achieved = per_kind[dom]["GB_per_s"]
     sweep_ms = float(np.median(stage["sweeps"]))
     lat_ms = np.array(lat) * 1000.0

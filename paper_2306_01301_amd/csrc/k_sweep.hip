@@ -33,6 +33,13 @@
 
 #include "nhp_internal.h"
 
+#ifndef XQ_COLS
+#define XQ_COLS 32
+#endif
+#ifndef XQ_THREADS
+#define XQ_THREADS 256
+#endif
+
 namespace nhp {
 namespace {
 
@@ -283,27 +290,29 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
 // four waves scan Q/4 columns each for all 64 lines (section composition in
 // LDS, carry from the previous chunk), write the results back into the tile,
 // and the tile is stored row by row.
-template <int Q>
+template <int Q, int NT>
 struct XShared {
   static constexpr int LINES = 64;
+  static constexpr int NW = NT / 64;  // waves
   static constexpr int R = LINES + Q;  // rows a chunk can touch (|B(c+1) - B(c)| <= 1)
   static constexpr int PITCH = Q + 1;  // odd pitch: a column read by 64 lanes hits 64 banks
   uint32_t tV[R * PITCH];
   uint8_t tB[R * PITCH];
   int32_t tS[Q];
-  uint32_t aggD[4][64];
-  uint32_t aggC[4][64];
+  uint32_t aggD[NW][64];
+  uint32_t aggC[NW][64];
   uint32_t wlut[256];
   int16_t skew[1024];  // B(c, T) of this plane
 };
 
-template <int Q>
-__device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, XShared<Q>& sh) {
-  using X = XShared<Q>;
-  constexpr int LINES = X::LINES, PITCH = X::PITCH;
-  constexpr int SUB = Q / 4;  // columns per wave
-  constexpr int ITER = (X::R * Q + 255) / 256;
-  static_assert(256 % Q == 0, "Q must divide 256");
+template <int Q, int NT>
+__device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, XShared<Q, NT>& sh) {
+  using X = XShared<Q, NT>;
+  constexpr int LINES = X::LINES, PITCH = X::PITCH, NW = X::NW;
+  constexpr int SUB = Q / NW;  // columns per wave
+  constexpr int ROWS = NT / Q;  // band rows per load round
+  constexpr int ITER = (X::R * Q + NT - 1) / NT;
+  static_assert(NT % Q == 0 && Q % NW == 0, "Q must divide the thread count and split over the waves");
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -312,14 +321,14 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
   const int T = a.planes[tile / a.tiles_x];
   const uint32_t plane = (uint32_t)T * (uint32_t)N * (uint32_t)N;
   const uint32_t Lq = a.edge_len[T];
-  sh.wlut[tid] = weight((uint32_t)tid, 256u * Lq + 128u, 4u * Lq);
+  for (int c = tid; c < 256; c += NT) sh.wlut[c] = weight((uint32_t)c, 256u * Lq + 128u, 4u * Lq);
   const int dir = (a.fwd[T] > 0) == (a.mu_forward != 0);
   const int16_t* skg = a.skew + (size_t)T * N;
-  for (int c = tid; c < N; c += 256) sh.skew[c] = skg[c];
+  for (int c = tid; c < N; c += NT) sh.skew[c] = skg[c];
   __syncthreads();
   const int16_t* sk = sh.skew;
   const int kk = tid % Q;  // column of this thread in the load/store phases
-  const int r0 = tid / Q;  // first row of this thread; rows r0 + it * (256 / Q)
+  const int r0 = tid / Q;  // first row of this thread; rows r0 + it * ROWS
   const bool line_ok = x0 + lane < N;
 
   uint32_t carry = kInf;  // value carried along line x0 + lane into the chunk
@@ -343,7 +352,7 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
     bool own[ITER];
 #pragma unroll
     for (int it = 0; it < ITER; it++) {
-      const int r = r0 + it * (256 / Q);
+      const int r = r0 + it * ROWS;
       const int t = r + bmin - my_b;
       own[it] = col_ok && r < rows && t >= 0 && t < LINES && x0 + t < N;
       int row = rowbase + r;
@@ -355,7 +364,7 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
 #pragma unroll
     for (int it = 0; it < ITER; it++) {
       if (own[it]) {
-        const int r = r0 + it * (256 / Q);
+        const int r = r0 + it * ROWS;
         sh.tV[r * PITCH + kk] = lv[it];
         sh.tB[r * PITCH + kk] = (uint8_t)lc[it];
       }
@@ -393,14 +402,14 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
         v = sadd(umin(v, sadd(u[q], a.ct)), w[q]);
       }
     }
-    for (int s = 0; s < 4; s++) carry = umin(sadd(carry, sh.aggD[s][lane]), sh.aggC[s][lane]);
+    for (int s = 0; s < NW; s++) carry = umin(sadd(carry, sh.aggD[s][lane]), sh.aggC[s][lane]);
     __syncthreads();
 
     // store the band back
 #pragma unroll
     for (int it = 0; it < ITER; it++) {
       if (own[it]) {
-        const int r = r0 + it * (256 / Q);
+        const int r = r0 + it * ROWS;
         st_value(a.V, cell[it], sh.tV[r * PITCH + kk]);
       }
     }
@@ -437,19 +446,19 @@ __global__ __launch_bounds__(1024) void row_sweep_batch_kernel(const SweepJob* _
   row_sweep_tile<P, FUSED, GUARD>(job, t - job.first_block, sh);
 }
 
-template <int Q>
-__global__ __launch_bounds__(256) void xmajor_sweep_kernel(SweepJob job) {
-  __shared__ XShared<Q> sh;
-  xmajor_sweep_tile<Q>(job, xcd_tile(blockIdx.x, gridDim.x), sh);
+template <int Q, int NT>
+__global__ __launch_bounds__(NT) void xmajor_sweep_kernel(SweepJob job) {
+  __shared__ XShared<Q, NT> sh;
+  xmajor_sweep_tile<Q, NT>(job, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
 
-template <int Q>
-__global__ __launch_bounds__(256) void xmajor_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs) {
-  __shared__ XShared<Q> sh;
+template <int Q, int NT>
+__global__ __launch_bounds__(NT) void xmajor_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs) {
+  __shared__ XShared<Q, NT> sh;
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
   const SweepJob job = jobs[j];
-  xmajor_sweep_tile<Q>(job, t - job.first_block, sh);
+  xmajor_sweep_tile<Q, NT>(job, t - job.first_block, sh);
 }
 
 __global__ void init_kernel(uint32_t* __restrict__ V, size_t n4, uint32_t start) {
@@ -498,7 +507,8 @@ __global__ void walls_kernel(uint8_t* __restrict__ B, int N, int L) {
   }
 }
 
-constexpr int XQ = 32;  // columns per x-major chunk
+constexpr int XQ = XQ_COLS;   // columns per x-major chunk
+constexpr int XNT = XQ_THREADS;  // threads per x-major workgroup
 
 }  // namespace
 
@@ -661,7 +671,7 @@ hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   if (xmaj.blocks) {
-    hipLaunchKernelGGL((xmajor_sweep_kernel<XQ>), dim3(xmaj.blocks), dim3(256), 0, s, xmaj);
+    hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT>), dim3(xmaj.blocks), dim3(XNT), 0, s, xmaj);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -687,7 +697,7 @@ hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_bloc
                               bool xmajor, hipStream_t s) {
   if (n_jobs == 0) return hipSuccess;
   if (xmajor) {
-    hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ>), dim3(total_blocks), dim3(256), 0, s, d_jobs, n_jobs);
+    hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT>), dim3(total_blocks), dim3(XNT), 0, s, d_jobs, n_jobs);
     return hipGetLastError();
   }
   if (fused)
