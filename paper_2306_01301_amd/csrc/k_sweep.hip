@@ -33,13 +33,6 @@
 
 #include "nhp_internal.h"
 
-#ifndef XQ_COLS
-#define XQ_COLS 32
-#endif
-#ifndef XQ_THREADS
-#define XQ_THREADS 256
-#endif
-
 namespace nhp {
 namespace {
 
@@ -61,6 +54,13 @@ __device__ __forceinline__ uint32_t ld_value(const uint32_t* V, uint32_t cell) {
 }
 __device__ __forceinline__ void st_value(uint32_t* V, uint32_t cell, uint32_t v) {
   *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(V) + (cell << 2)) = v;
+}
+
+// A column in [0, 2N) reduced to [0, N): the unsigned i - N wraps above i
+// whenever i < N, so the smaller of the two is the reduced column.
+__device__ __forceinline__ uint32_t wrap_col(uint32_t i, int N) {
+  const uint32_t j = i - (uint32_t)N;
+  return j < i ? j : i;
 }
 
 // Workgroup index spread over the 8 XCDs so that consecutive tiles (which
@@ -191,9 +191,7 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, RowShared& sh, u
 #pragma unroll
       for (int k = 0; k < P; k++) {
         if (!GUARD || k < n_real) {
-          int i = xs + (int)sh.shift[first + k];
-          i -= (i >= N) ? N : 0;
-          st_value(a.V, sh.row_base[first + k] + (uint32_t)i, u[k]);
+          st_value(a.V, sh.row_base[first + k] + wrap_col((uint32_t)xs + sh.shift[first + k], N), u[k]);
         }
       }
     }
@@ -270,10 +268,10 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
     const int xl = active ? xp : N - 1;
 #pragma unroll
     for (int k = 0; k < P; k++) {
-      const int s = (first + k) < L ? first + k : L - 1;
-      int i = xl + (int)sh.shift[s];
-      i -= (i >= N) ? N : 0;
-      const uint32_t cell = sh.row_base[s] + (uint32_t)i;
+      // full sections need no clamp, so the geometry reads take constant
+      // offsets from one address
+      const int s = (!GUARD || first + k < L) ? first + k : L - 1;
+      const uint32_t cell = sh.row_base[s] + wrap_col((uint32_t)xl + sh.shift[s], N);
       u[k] = ld_value(a.V, cell);
       code[k] = a.B[cell];
     }
@@ -431,19 +429,40 @@ __device__ __forceinline__ int find_job(const SweepJob* __restrict__ jobs, int n
   return lo;
 }
 
+// Workgroups stay resident and walk the tiles (the grid is capped near the
+// number that fits the chip at once): a tile's stores drain while the next
+// tile's loads are issued, and no workgroup launch separates them.  The
+// barrier keeps the LDS tables of the previous tile until every wave is done
+// with them.
 template <int P, bool FUSED, bool GUARD>
 __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepJob job) {
   __shared__ RowShared sh;
-  row_sweep_tile<P, FUSED, GUARD>(job, xcd_tile(blockIdx.x, gridDim.x), sh);
+  for (int b = blockIdx.x; b < job.blocks; b += gridDim.x) {
+    __syncthreads();
+    row_sweep_tile<P, FUSED, GUARD>(job, xcd_tile(b, job.blocks), sh);
+  }
 }
 
 template <int P, bool FUSED, bool GUARD>
-__global__ __launch_bounds__(1024) void row_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs) {
+__global__ __launch_bounds__(1024) void row_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs,
+                                                                 int total_blocks) {
   __shared__ RowShared sh;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
-  const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
-  const SweepJob job = jobs[j];
-  row_sweep_tile<P, FUSED, GUARD>(job, t - job.first_block, sh);
+  for (int b = blockIdx.x; b < total_blocks; b += gridDim.x) {
+    __syncthreads();
+    const int t = xcd_tile(b, total_blocks);
+    const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
+    const SweepJob job = jobs[j];
+    row_sweep_tile<P, FUSED, GUARD>(job, t - job.first_block, sh);
+  }
+}
+
+// Resident workgroups for a row launch: 256 CUs times the workgroups of
+// `waves` waves that fit one CU (at most 16 waves per CU at these register
+// counts, 32 for the small sections).
+int row_grid(int blocks, int waves, int P) {
+  const int per_cu = (P >= 32 ? 16 : 32) / waves;
+  const int cap = 256 * (per_cu > 0 ? per_cu : 1);
+  return blocks < cap ? blocks : cap;
 }
 
 template <int Q, int NT>
@@ -507,8 +526,10 @@ __global__ void walls_kernel(uint8_t* __restrict__ B, int N, int L) {
   }
 }
 
-constexpr int XQ = XQ_COLS;   // columns per x-major chunk
-constexpr int XNT = XQ_THREADS;  // threads per x-major workgroup
+// x-major chunks of 32 columns, 256 threads per workgroup (64 columns with
+// 512 threads and 32 columns with 512 threads measured slower)
+constexpr int XQ = 32;
+constexpr int XNT = 256;
 
 }  // namespace
 
@@ -617,7 +638,8 @@ int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj) 
 
 template <bool FUSED, bool GUARD>
 hipError_t launch_row_job_t(const SweepJob& j, hipStream_t s) {
-  const dim3 grid(j.blocks), block(64 * ((j.L + j.P - 1) / j.P));
+  const int waves = (j.L + j.P - 1) / j.P;
+  const dim3 grid(row_grid(j.blocks, waves, j.P)), block(64 * waves);
   switch (j.P) {
     case 64:
       if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
@@ -679,15 +701,15 @@ hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s) {
 
 template <bool FUSED, bool GUARD>
 hipError_t launch_row_batch_t(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, hipStream_t s) {
-  const dim3 grid(total_blocks), block(1024);
+  const dim3 grid(row_grid(total_blocks, 16, P)), block(1024);
   switch (P) {
     case 64:
       if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
-      hipLaunchKernelGGL((row_sweep_batch_kernel<64, false, GUARD>), grid, block, 0, s, d_jobs, n_jobs);
+      hipLaunchKernelGGL((row_sweep_batch_kernel<64, false, GUARD>), grid, block, 0, s, d_jobs, n_jobs, total_blocks);
       break;
-    case 32: hipLaunchKernelGGL((row_sweep_batch_kernel<32, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs); break;
-    case 16: hipLaunchKernelGGL((row_sweep_batch_kernel<16, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs); break;
-    case 8: hipLaunchKernelGGL((row_sweep_batch_kernel<8, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs); break;
+    case 32: hipLaunchKernelGGL((row_sweep_batch_kernel<32, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs, total_blocks); break;
+    case 16: hipLaunchKernelGGL((row_sweep_batch_kernel<16, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs, total_blocks); break;
+    case 8: hipLaunchKernelGGL((row_sweep_batch_kernel<8, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs, total_blocks); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
