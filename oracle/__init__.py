@@ -90,11 +90,15 @@ def _L():
         lib.or_goal_search.argtypes = [P(_Problem), vp, vp, i32, i32, i32, i32, u32, u32, vp, vp]
         lib.or_backtrack.argtypes = [P(_Problem), vp, vp, i32, i32, i32, vp, vp, i32, vp]
         lib.or_set_threads.argtypes = [i32]
+        lib.or_init_set.argtypes = [P(_Problem), vp, vp, vp, i32]
+        lib.or_goal_set.argtypes = [P(_Problem), vp, vp, vp, vp, i32, vp, vp]
+        lib.or_backtrack_set.argtypes = [P(_Problem), vp, vp, vp, i32, vp, vp, i32, vp]
         lib.or_reach.argtypes = [P(_Problem), vp, i32, i32, i32, i32, vp]
         lib.or_reach_goal.argtypes = [P(_Problem), vp, i32, i32, i32, i32, vp, vp]
         lib.or_reach_backtrack.argtypes = [P(_Problem), vp, vp, vp, vp, i32, vp]
         for name in ("or_tables_export", "or_render_taps", "or_render", "or_init", "or_sweep",
                      "or_cycles", "or_goal_search", "or_backtrack", "or_set_threads", "or_reach",
+                     "or_init_set", "or_goal_set", "or_backtrack_set",
                      "or_reach_goal", "or_reach_backtrack"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
@@ -274,5 +278,52 @@ def reach_backtrack(prob: Problem, B, level, best, cap: int = 1024) -> List[Step
     p = prob.c()
     _check(_L().or_reach_backtrack(ctypes.byref(p), _ptr(B), _ptr(level), _ptr(g), ctypes.addressof(steps),
                                    int(cap), ctypes.addressof(n)), "or_reach_backtrack")
+    return [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_), tuple(int(v) for v in s.to),
+                 int(s.cost)) for s in steps[: n.value]]
+
+
+# ---------------------------------------------------------------- start and goal sets
+
+class _Start(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_int32), ("j", ctypes.c_int32), ("T", ctypes.c_int32), ("cost", ctypes.c_uint32),
+                ("maneuver", ctypes.c_int32)]
+
+
+def _starts(starts):
+    """starts: sequence of (i, j, T, cost) or (i, j, T, cost, maneuver)."""
+    arr = (_Start * len(starts))()
+    for k, s in enumerate(starts):
+        mu = s[4] if len(s) > 4 else -1
+        arr[k] = _Start(int(s[0]), int(s[1]), int(s[2]), int(s[3]), int(mu))
+    return arr
+
+
+def init_set(prob: Problem, B: np.ndarray, starts) -> np.ndarray:
+    V = np.empty(B.shape, np.uint32)
+    p = prob.c()
+    arr = _starts(starts)
+    _check(_L().or_init_set(ctypes.byref(p), _ptr(B), _ptr(V), ctypes.addressof(arr), len(starts)), "or_init_set")
+    return V
+
+
+def goal_set(prob: Problem, B, V, goals, penalty):
+    g = np.ascontiguousarray(np.asarray(goals, np.int32).reshape(-1))
+    pen = np.ascontiguousarray(np.asarray(penalty, np.uint32))
+    k = np.zeros(1, np.int32)
+    sc = np.zeros(1, np.uint32)
+    p = prob.c()
+    _check(_L().or_goal_set(ctypes.byref(p), _ptr(B), _ptr(V), _ptr(g), _ptr(pen), len(pen), _ptr(k), _ptr(sc)),
+           "or_goal_set")
+    return int(k[0]), int(sc[0])
+
+
+def backtrack_set(prob: Problem, B, V, starts, best, cap: int = 4096) -> List[Step]:
+    steps = (_Step * max(cap, 1))()
+    n = ctypes.c_int32(0)
+    g = np.array(best, np.int32)
+    arr = _starts(starts)
+    p = prob.c()
+    _check(_L().or_backtrack_set(ctypes.byref(p), _ptr(B), _ptr(V), ctypes.addressof(arr), len(starts), _ptr(g),
+                                 ctypes.addressof(steps), int(cap), ctypes.addressof(n)), "or_backtrack_set")
     return [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_), tuple(int(v) for v in s.to),
                  int(s.cost)) for s in steps[: n.value]]

@@ -22,6 +22,8 @@
  *   cycles     Sec. XVI.A: N cycles of LF, SF, RB, RF, SB, LB.
  *   goal       Sec. IX: best vertex in a window around the goal.
  *   backtrack  Sec. X, eq. (32): reverse Bellman steps back to the start.
+ *   sets       Sec. III.A, IX, XII: start sets with costs (also inside a
+ *              maneuver in progress) and goal sets with penalties.
  *   reach      App. C, Insert 2: reachability by maneuver count (hard
  *              obstacles only), its goal search and back-tracking.
  *
@@ -685,6 +687,252 @@ int or_backtrack(const or_problem* p, const uint8_t* B, const uint32_t* V, int32
   if (rc) return rc;
   if (n > cap) return OR_ECAP;
   for (int32_t a = 0, b = n - 1; a < b; a++, b--) { /* start -> goal order */
+    or_step t = steps[a];
+    steps[a] = steps[b];
+    steps[b] = t;
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* exported: start sets and goal sets (Sec. III.A, IX, XII)           */
+/* ------------------------------------------------------------------ */
+
+/* A start: a pose with a cost, either at rest (maneuver < 0: the vehicle
+ * may begin any maneuver there, paying its transition cost) or inside a
+ * maneuver already in progress (Sec. XII: that maneuver continues without a
+ * transition cost).  The second kind seeds every pose the maneuver reaches
+ * from the start pose with cost + the edge sum so far, up to the first
+ * vertex in collision (one loop for turns, to the end of the line for
+ * straights). */
+typedef struct {
+  int32_t i, j, T;
+  uint32_t cost;
+  int32_t maneuver;
+} or_start;
+
+typedef struct {
+  size_t x;      /* pose index */
+  uint32_t value;
+  int32_t start; /* index of the start that seeded it */
+  int32_t k;     /* edges from the start pose along its maneuver */
+} or_seed;
+
+/* The k-th vertex after (i, j, T) on the curve of maneuver mu, in its
+ * direction of travel; 0 when the curve has no such vertex. */
+static int successor(const or_problem* p, const or_tables* tb, int mu, int32_t i, int32_t j, int32_t T, int32_t k,
+                     int32_t* qi, int32_t* qj, int32_t* qT) {
+  int32_t N = p->nx, L = p->nt;
+  if (is_turn(mu)) {
+    if (k >= L) return 0;
+    int left = turn_left(mu);
+    int32_t ox, oy, rx, ry;
+    turn_offset(p, tb, left, T, &ox, &oy);
+    int32_t xp = wrap((int64_t)i - ox, N), yp = wrap((int64_t)j - oy, N);
+    int32_t Tk = wrap(turn_ascending(mu) ? (int64_t)T + k : (int64_t)T - k, L);
+    turn_offset(p, tb, left, Tk, &rx, &ry);
+    *qi = wrap((int64_t)xp + rx, N);
+    *qj = wrap((int64_t)yp + ry, N);
+    *qT = Tk;
+    return 1;
+  }
+  int asc = straight_ascending(mu, tb->J[T]);
+  int32_t c = tb->I[T] == 0 ? i : j;
+  int32_t other = tb->I[T] == 0 ? j : i;
+  int32_t xp = wrap((int64_t)other - tb->Bsk[(size_t)T * N + c], N);
+  int32_t step = asc ? c : wrap(N - c, N);
+  if (step + k > N - 1) return 0;
+  straight_cell(p, tb, T, xp, straight_coord(N, asc, step + k), qi, qj);
+  *qT = T;
+  return 1;
+}
+
+/* Seeds of a start set, in start order and, per start, in k order.
+ * Returns the count (at most cap), or a negative status. */
+static int64_t make_seeds(const or_problem* p, const or_tables* tb, const uint8_t* B, const or_start* st, int32_t n,
+                          or_seed* seeds, int64_t cap) {
+  int64_t m = 0;
+  for (int32_t s = 0; s < n; s++) {
+    if (st[s].i < 0 || st[s].j < 0 || st[s].T < 0 || st[s].i >= p->nx || st[s].j >= p->nx || st[s].T >= p->nt ||
+        st[s].maneuver > 5)
+      return OR_EINVAL;
+    size_t x0 = cell_index(p, st[s].i, st[s].j, st[s].T);
+    if (B[x0] == OR_HARD) return OR_ESTART;
+    if (m >= cap) return OR_ECAP;
+    seeds[m++] = (or_seed){x0, st[s].cost, s, 0};
+    int mu = st[s].maneuver;
+    if (mu < 0) continue;
+    uint32_t E = 0;
+    int32_t ci = st[s].i, cj = st[s].j, cT = st[s].T;
+    for (int32_t k = 1;; k++) {
+      int32_t qi, qj, qT;
+      E = sat_add(E, edge_weight(tb->Lq[(size_t)mu * p->nt + cT], B[cell_index(p, ci, cj, cT)]));
+      if (E == OR_INF) break;
+      if (!successor(p, tb, mu, st[s].i, st[s].j, st[s].T, k, &qi, &qj, &qT)) break;
+      size_t q = cell_index(p, qi, qj, qT);
+      if (B[q] == OR_HARD) break;
+      if (m >= cap) return OR_ECAP;
+      seeds[m++] = (or_seed){q, sat_add(st[s].cost, E), s, k};
+      ci = qi;
+      cj = qj;
+      cT = qT;
+    }
+  }
+  return m;
+}
+
+/* V = infinity, then every seed lowers its pose to its value. */
+int or_init_set(const or_problem* p, const uint8_t* B, uint32_t* V, const or_start* st, int32_t n) {
+  int rc = check_problem(p);
+  if (rc) return rc;
+  if (n < 1) return OR_EINVAL;
+  or_tables tb;
+  rc = tables_build(p, &tb);
+  int64_t cap = (int64_t)n * ((p->nx > p->nt ? p->nx : p->nt) + 1);
+  or_seed* seeds = (or_seed*)malloc(sizeof(or_seed) * (size_t)cap);
+  if (rc == OR_OK && !seeds) rc = OR_ENOMEM;
+  if (rc == OR_OK) {
+    int64_t m = make_seeds(p, &tb, B, st, n, seeds, cap);
+    if (m < 0) {
+      rc = (int)m;
+    } else {
+      size_t NR = (size_t)p->nx * p->nx * p->nt;
+      for (size_t x = 0; x < NR; x++) V[x] = OR_INF;
+      for (int64_t e = 0; e < m; e++) V[seeds[e].x] = umin(V[seeds[e].x], seeds[e].value);
+    }
+  }
+  free(seeds);
+  tables_free(&tb);
+  return rc;
+}
+
+/* Goal set with penalties (a reward expressed as its shortfall from the
+ * largest reward, Sec. IX): the goal minimising V + penalty, skipping goals
+ * in collision or unreached; ties go to the earlier goal. */
+int or_goal_set(const or_problem* p, const uint8_t* B, const uint32_t* V, const int32_t* goals,
+                const uint32_t* penalty, int32_t n, int32_t* best_k, uint32_t* score) {
+  int rc = check_problem(p);
+  if (rc) return rc;
+  int found = 0;
+  uint32_t bs = OR_INF;
+  for (int32_t k = 0; k < n; k++) {
+    int32_t i = goals[3 * k], j = goals[3 * k + 1], T = goals[3 * k + 2];
+    if (i < 0 || j < 0 || T < 0 || i >= p->nx || j >= p->nx || T >= p->nt) return OR_EINVAL;
+    size_t x = cell_index(p, i, j, T);
+    if (B[x] == OR_HARD || V[x] == OR_INF) continue;
+    uint32_t sc = sat_add(V[x], penalty[k]);
+    if (!found || sc < bs) {
+      found = 1;
+      bs = sc;
+      *best_k = k;
+    }
+  }
+  if (!found) return OR_EUNREACH;
+  *score = bs;
+  return OR_OK;
+}
+
+/* Back-tracking to a start set: the walk of or_backtrack, ending at the
+ * first pose that is a seed whose value equals V there (first seed in seed
+ * order).  A seed inside an in-progress maneuver adds that maneuver's
+ * steps from the start pose (cost: the edge sum, no transition). */
+int or_backtrack_set(const or_problem* p, const uint8_t* B, const uint32_t* V, const or_start* st, int32_t n_st,
+                     const int32_t* goal, or_step* steps, int32_t cap, int32_t* n_steps) {
+  int rc = check_problem(p);
+  if (rc) return rc;
+  int32_t N = p->nx, L = p->nt;
+  or_tables tb;
+  rc = tables_build(p, &tb);
+  int64_t scap = (int64_t)n_st * ((N > L ? N : L) + 1);
+  or_seed* seeds = (or_seed*)malloc(sizeof(or_seed) * (size_t)scap);
+  int64_t m = 0;
+  if (rc == OR_OK && !seeds) rc = OR_ENOMEM;
+  if (rc == OR_OK) {
+    m = make_seeds(p, &tb, B, st, n_st, seeds, scap);
+    if (m < 0) rc = (int)m;
+  }
+  int32_t ci = goal[0], cj = goal[1], cT = goal[2];
+  int32_t n = 0;
+  int32_t limit = 1 << 20;
+  int64_t hit = -1;
+  while (rc == OR_OK) {
+    size_t cx = cell_index(p, ci, cj, cT);
+    for (int64_t e = 0; e < m && hit < 0; e++)
+      if (seeds[e].x == cx && seeds[e].value == V[cx]) hit = e;
+    if (hit >= 0) break;
+    if (V[cx] == OR_INF || n >= limit) {
+      rc = OR_EUNREACH;
+      break;
+    }
+    uint32_t bc = OR_INF, bcost = 0;
+    int32_t bk = 0, bi = 0, bj = 0, bT = 0, bmu = -1;
+    int32_t maxk = N > L ? N : L;
+    for (int32_t pos = 0; pos < p->nsched; pos++) {
+      int mu = p->sched[pos];
+      uint32_t E = 0;
+      for (int32_t k = 1; k <= maxk; k++) {
+        int32_t qi, qj, qT;
+        if (!predecessor(p, &tb, mu, ci, cj, cT, k, &qi, &qj, &qT)) break;
+        size_t q = cell_index(p, qi, qj, qT);
+        E = sat_add(E, edge_weight(tb.Lq[(size_t)mu * L + qT], B[q]));
+        if (E == OR_INF) break;
+        uint32_t cand = sat_add(sat_add(V[q], p->ct[mu]), E);
+        if (cand < bc) {
+          bc = cand;
+          bk = k;
+          bmu = mu;
+          bi = qi;
+          bj = qj;
+          bT = qT;
+          bcost = sat_add(p->ct[mu], E);
+        }
+      }
+    }
+    if (bmu < 0 || bc == OR_INF) {
+      rc = OR_EUNREACH;
+      break;
+    }
+    if (n < cap) {
+      or_step* sp = &steps[n];
+      memset(sp, 0, sizeof(*sp));
+      sp->maneuver = (uint8_t)bmu;
+      sp->steps = (uint32_t)bk;
+      sp->from[0] = (uint32_t)bi;
+      sp->from[1] = (uint32_t)bj;
+      sp->from[2] = (uint32_t)bT;
+      sp->to[0] = (uint32_t)ci;
+      sp->to[1] = (uint32_t)cj;
+      sp->to[2] = (uint32_t)cT;
+      sp->cost = bcost;
+    }
+    n++;
+    ci = bi;
+    cj = bj;
+    cT = bT;
+  }
+  if (rc == OR_OK && seeds[hit].k > 0) { /* the maneuver already in progress */
+    const or_start* s0 = &st[seeds[hit].start];
+    if (n < cap) {
+      or_step* sp = &steps[n];
+      memset(sp, 0, sizeof(*sp));
+      sp->maneuver = (uint8_t)s0->maneuver;
+      sp->steps = (uint32_t)seeds[hit].k;
+      sp->from[0] = (uint32_t)s0->i;
+      sp->from[1] = (uint32_t)s0->j;
+      sp->from[2] = (uint32_t)s0->T;
+      sp->to[0] = (uint32_t)ci;
+      sp->to[1] = (uint32_t)cj;
+      sp->to[2] = (uint32_t)cT;
+      sp->cost = seeds[hit].value - s0->cost;
+    }
+    n++;
+  }
+  free(seeds);
+  tables_free(&tb);
+  *n_steps = n;
+  if (rc) return rc;
+  if (n > cap) return OR_ECAP;
+  for (int32_t a = 0, b = n - 1; a < b; a++, b--) {
     or_step t = steps[a];
     steps[a] = steps[b];
     steps[b] = t;

@@ -220,3 +220,52 @@ def path_cost(g: Graph, start: int, steps) -> list:
             x = int(g.succ[mu][x])
         out.append((x, min(E + g.ct[mu], INF)))
     return out
+
+
+def star_dijkstra_sources(g: Graph, schedule, sources) -> np.ndarray:
+    """Star-graph Dijkstra from several sources: (x, d, mu) puts distance d
+    on the transition vertex of x (mu < 0) or on its maneuver-mu vertex
+    (a maneuver already in progress: it continues along mu's edges, and
+    leaving it costs nothing).  Transition -> maneuver edges exist for the
+    scheduled maneuvers only."""
+    NR = g.succ.shape[1]
+    sched = sorted(set(int(m) for m in schedule))
+    mus = sorted(set(sched) | {int(m) for _, _, m in sources if m >= 0})
+    dT = np.full(NR, INF, np.int64)
+    dM = {mu: np.full(NR, INF, np.int64) for mu in mus}
+    heap = []
+    for x, d, mu in sources:
+        if mu < 0:
+            if d < dT[x]:
+                dT[x] = d
+                heapq.heappush(heap, (d, 0, x))
+        elif d < dM[mu][x]:
+            dM[mu][x] = d
+            heapq.heappush(heap, (d, 1 + mu, x))
+    while heap:
+        d, kind, x = heapq.heappop(heap)
+        if kind == 0:
+            if d != dT[x]:
+                continue
+            for mu in sched:
+                nd = d + g.ct[mu]
+                if nd < dM[mu][x]:
+                    dM[mu][x] = nd
+                    heapq.heappush(heap, (nd, 1 + mu, x))
+        else:
+            mu = kind - 1
+            if d != dM[mu][x]:
+                continue
+            if d < dT[x] and g.B[x] != HARD:
+                dT[x] = d
+                heapq.heappush(heap, (d, 0, x))
+            we = int(g.w[mu][x])
+            if we < INF:
+                y = int(g.succ[mu][x])
+                nd = d + we
+                if nd < dM[mu][y]:
+                    dM[mu][y] = nd
+                    heapq.heappush(heap, (nd, 1 + mu, y))
+    out = np.minimum(dT, INF)
+    out[g.B == HARD] = INF
+    return out
