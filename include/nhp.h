@@ -131,6 +131,33 @@ int plan_set_cspace(nhp_plan* plan, const uint8_t* d_cspace);
  * collision; checked on the host, which synchronises once), NHP_EHIP. */
 int sweep_n_turns(nhp_plan* plan, uint32_t si, uint32_t sj, uint32_t st, uint32_t n_cycles);
 
+/* A start of a start set (Sec. III.A: start states with a cost depending on
+ * where the plan begins; Sec. XII: a maneuver already in progress).
+ * maneuver = -1: the vehicle is at rest at (i, j, T) with cost cost_q10 and
+ * may begin any scheduled maneuver there (paying its transition cost).
+ * maneuver = 0..5: that maneuver is in progress at (i, j, T); it continues
+ * without a transition cost, so every pose it reaches along its curve (up to
+ * the first pose in collision; one loop for turns, the end of the line for
+ * straights) starts at cost_q10 plus the edge sum from (i, j, T). */
+typedef struct {
+  uint32_t i, j, T;
+  uint32_t cost_q10;
+  int32_t maneuver;
+} nhp_start;
+
+#define NHP_MAX_STARTS 64u
+#define NHP_MAX_GOALS 4096u
+
+/* Like sweep_n_turns from a start set of n_starts (1..NHP_MAX_STARTS)
+ * entries: V = NHP_INF, every start (and every pose of a maneuver in
+ * progress) lowered to its cost, then n_cycles cycles.  extract_path and
+ * extract_path_set then end a plan at the first start-set pose (in start
+ * order, then along the maneuver in progress) whose value equals its start
+ * cost; a maneuver in progress becomes the plan's first step (cost: its
+ * edge sum, no transition).  Errors: NHP_EINVAL, NHP_ESTART (a start pose in
+ * collision), NHP_ESTATE, NHP_EHIP. */
+int sweep_from_set(nhp_plan* plan, const nhp_start* h_starts, uint32_t n_starts, uint32_t n_cycles);
+
 /* Runs n_more_cycles further cycles on the current value volume without
  * re-initialising it (sweep_n_turns(a) then sweep_resume(b) equals
  * sweep_n_turns(a + b)).  Errors: NHP_ESTATE. */
@@ -180,6 +207,18 @@ int extract_path(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t
 
 /* Device pointers of the plan's value and obstacle volumes (for parity
  * checks and checkpoints; owned by the plan).  Either output may be NULL. */
+/* Goal set with penalties (Sec. IX: the criterion is the reward of the
+ * final vertex minus the cost to get there; a reward is passed as its
+ * shortfall from the largest reward, so penalty_q10 >= 0): the goal k
+ * (0 <= k < n_goals <= NHP_MAX_GOALS, goals_ijt[3k..]) minimising
+ * V + penalty (saturating) among goals that are free and reached, ties to
+ * the earlier goal; then back-tracking as extract_path.  *best_index = k,
+ * *goal_value_q10 = V(goal k), *score_q10 = V + penalty.  Errors as
+ * extract_path. */
+int extract_path_set(nhp_plan* plan, const uint32_t* goals_ijt, const uint32_t* penalty_q10, uint32_t n_goals,
+                     nhp_step* h_steps, uint32_t cap, uint32_t* n_steps, uint32_t* best_index,
+                     uint32_t* goal_value_q10, uint32_t* score_q10);
+
 int plan_device_ptrs(const nhp_plan* plan, uint32_t** d_value, uint8_t** d_cspace);
 
 /* Copies the host tables out (each host array may be NULL):

@@ -132,52 +132,178 @@ __device__ bool predecessor(const DevPlan& d, int mu, int i, int j, int T, int k
   return true;
 }
 
+// k-th pose after (i, j, T) on the curve of maneuver mu, in the maneuver's
+// direction of travel; false if the curve has no such pose (a turn closes
+// after L - 1 steps, a straight line ends at its far end).
+__device__ bool successor(const DevPlan& d, int mu, int i, int j, int T, int k, int* qi, int* qj, int* qT) {
+  const int N = d.nx, L = d.nt;
+  if (mu != NHP_SF && mu != NHP_SB) {
+    if (k >= L) return false;
+    const bool left = (mu == NHP_LF || mu == NHP_LB);
+    const bool asc = (mu == NHP_LF || mu == NHP_RB);
+    const int32_t* ox = d.turn_off + (left ? 0 : 2) * L;
+    const int32_t* oy = d.turn_off + (left ? 1 : 3) * L;
+    const int xp = wrapn(i - ox[T], N), yp = wrapn(j - oy[T], N);
+    const int Tk = wrapn(asc ? T + k : T - k, L);
+    *qi = wrapn(xp + ox[Tk], N);
+    *qj = wrapn(yp + oy[Tk], N);
+    *qT = Tk;
+    return true;
+  }
+  const bool fam_x = d.family[T] == 0;
+  const bool asc = (d.fwd[T] > 0) == (mu == NHP_SF);
+  const int16_t* sk = d.skew + (size_t)T * N;
+  const int c = fam_x ? i : j;
+  const int other = fam_x ? j : i;
+  const int xp = wrapn(other - sk[c], N);
+  // position along the sweep: upward lines start at 0, downward ones at 0 in
+  // the wall and then N - 1, N - 2, ...
+  const int step = asc ? c : (c == 0 ? 0 : N - c);
+  if (step + k > N - 1) return false;
+  const int s2 = step + k;
+  const int c2 = asc ? s2 : (s2 == 0 ? 0 : N - s2);
+  const int o2 = wrapn(xp + sk[c2], N);
+  *qi = fam_x ? c2 : o2;
+  *qj = fam_x ? o2 : c2;
+  *qT = T;
+  return true;
+}
+
+// Seeds of a start set: block s walks start s's maneuver in progress (thread
+// k takes the k-th pose; a block-wide saturating prefix sum gives the edge
+// sums), lowers V at every reachable pose to cost + edge sum and records the
+// seed; a start at rest seeds its own pose only.
+__global__ __launch_bounds__(kThreads) void seed_kernel(DevPlan d) {
+  __shared__ uint32_t red32[6][kWaves];
+  const int s = blockIdx.x, k = threadIdx.x;
+  const nhp_start st = d.starts[s];
+  const int mu = st.maneuver;
+  int qi = (int)st.i, qj = (int)st.j, qT = (int)st.T;
+  bool ok = k == 0;
+  if (k > 0 && mu >= 0 && k < d.seed_slots) ok = successor(d, mu, (int)st.i, (int)st.j, (int)st.T, k, &qi, &qj, &qT);
+  // weight of the edge leaving pose k (source weight), summed over 0..k
+  uint32_t w[1] = {kInf};
+  if (ok && mu >= 0) w[0] = weight(d.B[pose_index(d.nx, qi, qj, qT)], d.edge_len[(size_t)mu * d.nt + qT]);
+  uint32_t incl[1] = {w[0]};
+  block_scan_sat<1>(incl, red32);
+  // edge sum from pose 0 to pose k: the inclusive sum through pose k - 1
+  __shared__ uint32_t sums[kThreads];
+  sums[k] = incl[0];
+  __syncthreads();
+  const uint32_t E = k == 0 ? 0u : sums[k - 1];
+  uint32_t* sd = d.seeds + ((size_t)s * d.seed_slots + k) * kSeedWords;
+  const bool seed = ok && E != kInf && d.B[pose_index(d.nx, qi, qj, qT)] != kHard;
+  if (k < d.seed_slots) {
+    const uint32_t q = (uint32_t)pose_index(d.nx, qi, qj, qT);
+    const uint32_t v = sadd(st.cost_q10, E);
+    sd[0] = seed ? q : kNoSeed;
+    sd[1] = v;
+    sd[2] = (uint32_t)s;
+    sd[3] = (uint32_t)k;
+    if (seed) atomicMin(d.V + q, v);
+  }
+}
+
 __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[kWaves], uint64_t* red64) {
   const DevPlan& d = x.d;
   const int N = d.nx, L = d.nt;
   const int tid = threadIdx.x;
   uint32_t* out = d.extract;
 
-  // ---- goal search over the (2r+1)^3 window ----
-  const int r = x.radius, W = 2 * r + 1, nc = W * W * W;
-  uint64_t key = ~0ull;
-  for (int c = tid; c < nc; c += kThreads) {
-    const int dx = c % W - r, dy = (c / W) % W - r, dt = c / (W * W) - r;
-    const int i = modn((int)x.gi + dx, N), j = modn((int)x.gj + dy, N), T = modn((int)x.gt + dt, L);
-    const size_t q = pose_index(N, i, j, T);
-    const uint32_t v = d.V[q];
-    if (d.B[q] == kHard || v == kInf) continue;
-    const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy, at = dt < 0 ? -dt : dt;
-    const uint64_t pen = (uint64_t)x.w_xy * (uint64_t)(ax + ay) + (uint64_t)x.w_t * (uint64_t)at;
-    const uint32_t score = sadd(v, pen >= kInf ? kInf : (uint32_t)pen);
-    const uint64_t k2 = ((uint64_t)score << 32) | ((uint64_t)(ax + ay + at) << 18) |
-                        ((uint64_t)(dt + r) << 12) | ((uint64_t)(dy + r) << 6) | (uint64_t)(dx + r);
-    key = k2 < key ? k2 : key;
-  }
-  key = block_min_u64(key, red64);
-  if (key == ~0ull) {
-    if (tid == 0) {
-      out[0] = (uint32_t)(-NHP_EUNREACH);
-      out[1] = 0;
+  int ci, cj, cT;
+  if (x.n_goals > 0) {
+    // ---- goal set: smallest V + penalty, ties to the earlier goal ----
+    uint64_t key = ~0ull;
+    for (int k = tid; k < x.n_goals; k += kThreads) {
+      const uint32_t* g = d.goals + 4 * (size_t)k;
+      const size_t q = pose_index(N, (int)g[0], (int)g[1], (int)g[2]);
+      const uint32_t v = d.V[q];
+      if (d.B[q] == kHard || v == kInf) continue;
+      const uint64_t k2 = ((uint64_t)sadd(v, g[3]) << 12) | (uint64_t)k;
+      key = k2 < key ? k2 : key;
     }
-    return;
-  }
-  int ci = modn((int)x.gi + (int)(key & 63) - r, N);
-  int cj = modn((int)x.gj + (int)((key >> 6) & 63) - r, N);
-  int cT = modn((int)x.gt + (int)((key >> 12) & 63) - r, L);
-  if (tid == 0) {
-    out[2] = ci;
-    out[3] = cj;
-    out[4] = cT;
-    out[5] = d.V[pose_index(N, ci, cj, cT)];
-    out[6] = (uint32_t)(key >> 32);
+    key = block_min_u64(key, red64);
+    if (key == ~0ull) {
+      if (tid == 0) {
+        out[0] = (uint32_t)(-NHP_EUNREACH);
+        out[1] = 0;
+      }
+      return;
+    }
+    const uint32_t* g = d.goals + 4 * (size_t)(key & 4095);
+    ci = (int)g[0];
+    cj = (int)g[1];
+    cT = (int)g[2];
+    if (tid == 0) {
+      out[2] = ci;
+      out[3] = cj;
+      out[4] = cT;
+      out[5] = d.V[pose_index(N, ci, cj, cT)];
+      out[6] = (uint32_t)(key >> 12);
+      out[7] = (uint32_t)(key & 4095);
+    }
+  } else {
+    // ---- goal search over the (2r+1)^3 window ----
+    const int r = x.radius, W = 2 * r + 1, nc = W * W * W;
+    uint64_t key = ~0ull;
+    for (int c = tid; c < nc; c += kThreads) {
+      const int dx = c % W - r, dy = (c / W) % W - r, dt = c / (W * W) - r;
+      const int i = modn((int)x.gi + dx, N), j = modn((int)x.gj + dy, N), T = modn((int)x.gt + dt, L);
+      const size_t q = pose_index(N, i, j, T);
+      const uint32_t v = d.V[q];
+      if (d.B[q] == kHard || v == kInf) continue;
+      const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy, at = dt < 0 ? -dt : dt;
+      const uint64_t pen = (uint64_t)x.w_xy * (uint64_t)(ax + ay) + (uint64_t)x.w_t * (uint64_t)at;
+      const uint32_t score = sadd(v, pen >= kInf ? kInf : (uint32_t)pen);
+      const uint64_t k2 = ((uint64_t)score << 32) | ((uint64_t)(ax + ay + at) << 18) |
+                          ((uint64_t)(dt + r) << 12) | ((uint64_t)(dy + r) << 6) | (uint64_t)(dx + r);
+      key = k2 < key ? k2 : key;
+    }
+    key = block_min_u64(key, red64);
+    if (key == ~0ull) {
+      if (tid == 0) {
+        out[0] = (uint32_t)(-NHP_EUNREACH);
+        out[1] = 0;
+      }
+      return;
+    }
+    ci = modn((int)x.gi + (int)(key & 63) - r, N);
+    cj = modn((int)x.gj + (int)((key >> 6) & 63) - r, N);
+    cT = modn((int)x.gt + (int)((key >> 12) & 63) - r, L);
+    if (tid == 0) {
+      out[2] = ci;
+      out[3] = cj;
+      out[4] = cT;
+      out[5] = d.V[pose_index(N, ci, cj, cT)];
+      out[6] = (uint32_t)(key >> 32);
+      out[7] = 0;
+    }
   }
 
   // ---- back-tracking ----
   uint32_t n = 0, status = 0;
   const int k = tid + 1;
+  int seed_hit = -1;  // seed slot the plan ends at (start sets)
   for (uint32_t iter = 0;; iter++) {
-    if ((uint32_t)ci == x.si && (uint32_t)cj == x.sj && (uint32_t)cT == x.st) break;
+    if (x.n_starts > 0) {
+      // the first seed (start order, then along a maneuver in progress) at
+      // this pose whose value is the current value ends the plan
+      const uint32_t cur = (uint32_t)pose_index(N, ci, cj, cT);
+      const uint32_t vcur = d.V[cur];
+      uint64_t hit = ~0ull;
+      const int slots = x.n_starts * d.seed_slots;
+      for (int e = tid; e < slots; e += kThreads) {
+        const uint32_t* sd = d.seeds + (size_t)e * kSeedWords;
+        if (sd[0] == cur && sd[1] == vcur) hit = hit < (uint64_t)e ? hit : (uint64_t)e;
+      }
+      hit = block_min_u64(hit, red64);
+      if (hit != ~0ull) {
+        seed_hit = (int)hit;
+        break;
+      }
+    } else if ((uint32_t)ci == x.si && (uint32_t)cj == x.sj && (uint32_t)cT == x.st) {
+      break;
+    }
     // every step strictly lowers the value (edges cost >= 1), so a plan from
     // a swept volume ends well within the step buffer; the bound only stops
     // a walk over a value volume that no sweep produced
@@ -242,6 +368,26 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
     ci = pi;
     cj = pj;
     cT = pT;
+  }
+  if (seed_hit >= 0 && status == 0) {
+    // a seed inside a maneuver in progress: that maneuver is the first step
+    const uint32_t* sd = d.seeds + (size_t)seed_hit * kSeedWords;
+    const nhp_start st = d.starts[sd[2]];
+    if (sd[3] > 0) {
+      if (tid == 0 && n < NHP_MAX_STEPS_DEVICE) {
+        uint32_t* o = out + kExHeader + (size_t)n * kExStepWords;
+        o[0] = (uint32_t)st.maneuver;
+        o[1] = sd[3];
+        o[2] = st.i;
+        o[3] = st.j;
+        o[4] = st.T;
+        o[5] = ci;
+        o[6] = cj;
+        o[7] = cT;
+        o[8] = sd[1] - st.cost_q10;
+      }
+      n++;
+    }
   }
   if (tid == 0) {
     out[0] = status;
@@ -392,10 +538,13 @@ hipError_t launch_reach_extract(const ReachExArgs& x, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_extract(const DevPlan& d, uint32_t si, uint32_t sj, uint32_t st, uint32_t gi, uint32_t gj,
-                          uint32_t gt, int radius, uint32_t w_xy, uint32_t w_t, hipStream_t s) {
-  ExArgs x{d, si, sj, st, gi, gj, gt, radius, w_xy, w_t};
+hipError_t launch_extract(const ExArgs& x, hipStream_t s) {
   hipLaunchKernelGGL(extract_kernel, dim3(1), dim3(kThreads), 0, s, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(const DevPlan& d, int n_starts, hipStream_t s) {
+  hipLaunchKernelGGL(seed_kernel, dim3(n_starts), dim3(kThreads), 0, s, d);
   return hipGetLastError();
 }
 

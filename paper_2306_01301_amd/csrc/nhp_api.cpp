@@ -57,8 +57,10 @@ int hip_fail(hipError_t e, const char* what) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t V, B, turn_off, skew, edge_len, fwd, family, planes, taps, extract, total;
+  size_t V, B, turn_off, skew, edge_len, fwd, family, planes, taps, extract, starts, seeds, goals, total;
 };
+
+int seed_slots_of(const nhp_params& p) { return (int)(p.nx > p.ntheta ? p.nx : p.ntheta); }
 
 int check_params(const nhp_params* p) {
   if (!p) return fail(NHP_EINVAL, "params is NULL");
@@ -100,6 +102,12 @@ Layout layout_of(const nhp_params& p) {
   o = align256(o + (size_t)p.ntheta * 2 * nhp::kMaxTaps * 4);
   l.extract = o;
   o = align256(o + (nhp::kExHeader + (size_t)NHP_MAX_STEPS_DEVICE * nhp::kExStepWords) * 4);
+  l.starts = o;
+  o = align256(o + NHP_MAX_STARTS * sizeof(nhp_start));
+  l.seeds = o;
+  o = align256(o + (size_t)NHP_MAX_STARTS * seed_slots_of(p) * nhp::kSeedWords * 4);
+  l.goals = o;
+  o = align256(o + (size_t)NHP_MAX_GOALS * 4 * 4);
   l.total = o;
   return l;
 }
@@ -110,6 +118,9 @@ int check_plan(const nhp_plan* plan) {
 }
 
 }  // namespace
+
+static int finish_extract(nhp_plan* plan, nhp_step* h_steps, uint32_t cap, uint32_t* n_steps, uint32_t* best_ijt,
+                          uint32_t* best_index, uint32_t* goal_value_q10, uint32_t* score_q10);
 
 extern "C" {
 
@@ -177,6 +188,10 @@ int plan_create(const nhp_params* params, void* d_workspace, size_t workspace_by
   d.planes = reinterpret_cast<int32_t*>(base + l.planes);
   d.taps = reinterpret_cast<int32_t*>(base + l.taps);
   d.extract = reinterpret_cast<uint32_t*>(base + l.extract);
+  d.starts = reinterpret_cast<nhp_start*>(base + l.starts);
+  d.seeds = reinterpret_cast<uint32_t*>(base + l.seeds);
+  d.goals = reinterpret_cast<uint32_t*>(base + l.goals);
+  d.seed_slots = seed_slots_of(*params);
   d.n_planes_x = (int)plan->t.planes_x.size();
   d.n_planes_y = (int)plan->t.planes_y.size();
   for (int mu = 0; mu < 6; mu++) {
@@ -355,9 +370,42 @@ int sweep_n_turns(nhp_plan* plan, uint32_t si, uint32_t sj, uint32_t st, uint32_
   HIP_CHECK(hipStreamSynchronize(plan->stream), "start check");
   if (code == NHP_HARD) return fail(NHP_ESTART, "start pose (%u, %u, %u) is in collision", si, sj, st);
   HIP_CHECK(nhp::launch_init(plan->d, (uint32_t)s, plan->stream), "init launch");
+  plan->n_starts = 0;
   plan->start[0] = si;
   plan->start[1] = sj;
   plan->start[2] = st;
+  plan->has_value = true;
+  return (rc = run_cycles(plan, n_cycles)) ? rc : ok();
+}
+
+int sweep_from_set(nhp_plan* plan, const nhp_start* h_starts, uint32_t n_starts, uint32_t n_cycles) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!plan->has_cspace) return fail(NHP_ESTATE, "sweep_from_set before render_cspace/plan_set_cspace");
+  if (!h_starts || n_starts < 1 || n_starts > NHP_MAX_STARTS)
+    return fail(NHP_EINVAL, "1..%u starts needed (got %u)", NHP_MAX_STARTS, n_starts);
+  std::vector<uint8_t> codes(n_starts);
+  for (uint32_t k = 0; k < n_starts; k++) {
+    const nhp_start& st = h_starts[k];
+    if (st.i >= plan->p.nx || st.j >= plan->p.nx || st.T >= plan->p.ntheta)
+      return fail(NHP_EINVAL, "start %u outside the grid", k);
+    if (st.maneuver < -1 || st.maneuver > 5) return fail(NHP_EINVAL, "start %u: maneuver must be -1..5", k);
+    const size_t idx = ((size_t)st.T * plan->p.nx + st.j) * plan->p.nx + st.i;
+    HIP_CHECK(hipMemcpyAsync(&codes[k], plan->d.B + idx, 1, hipMemcpyDeviceToHost, plan->stream), "start check");
+  }
+  HIP_CHECK(hipMemcpyAsync(plan->d.starts, h_starts, n_starts * sizeof(nhp_start), hipMemcpyHostToDevice,
+                           plan->stream),
+            "start upload");
+  HIP_CHECK(hipStreamSynchronize(plan->stream), "start check");
+  for (uint32_t k = 0; k < n_starts; k++)
+    if (codes[k] == NHP_HARD) return fail(NHP_ESTART, "start %u is in collision", k);
+  // init with the start pose outside the volume: V = INF everywhere
+  HIP_CHECK(nhp::launch_init(plan->d, 0xFFFFFFFFu, plan->stream), "init launch");
+  HIP_CHECK(nhp::launch_seed(plan->d, (int)n_starts, plan->stream), "seed launch");
+  plan->n_starts = (int)n_starts;
+  plan->start[0] = h_starts[0].i;
+  plan->start[1] = h_starts[0].j;
+  plan->start[2] = h_starts[0].T;
   plan->has_value = true;
   return (rc = run_cycles(plan, n_cycles)) ? rc : ok();
 }
@@ -413,9 +461,26 @@ int extract_path(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t
   if (gi >= plan->p.nx || gj >= plan->p.nx || gt >= plan->p.ntheta) return fail(NHP_EINVAL, "goal outside the grid");
   if (radius > (uint32_t)nhp::kMaxRadius) return fail(NHP_EINVAL, "goal radius must be 0..%d", nhp::kMaxRadius);
   if (cap > 0 && !h_steps) return fail(NHP_EINVAL, "h_steps is NULL");
-  HIP_CHECK(nhp::launch_extract(plan->d, plan->start[0], plan->start[1], plan->start[2], gi, gj, gt, (int)radius,
-                                w_xy_q10, w_t_q10, plan->stream),
-            "extract launch");
+  nhp::ExArgs x{};
+  x.d = plan->d;
+  x.si = plan->start[0];
+  x.sj = plan->start[1];
+  x.st = plan->start[2];
+  x.gi = gi;
+  x.gj = gj;
+  x.gt = gt;
+  x.radius = (int)radius;
+  x.w_xy = w_xy_q10;
+  x.w_t = w_t_q10;
+  x.n_starts = plan->n_starts;
+  HIP_CHECK(nhp::launch_extract(x, plan->stream), "extract launch");
+  return finish_extract(plan, h_steps, cap, n_steps, best_ijt, nullptr, goal_value_q10, score_q10);
+}
+
+// Reads back the result of an extract launch: header, then the steps in
+// start -> goal order.
+static int finish_extract(nhp_plan* plan, nhp_step* h_steps, uint32_t cap, uint32_t* n_steps, uint32_t* best_ijt,
+                          uint32_t* best_index, uint32_t* goal_value_q10, uint32_t* score_q10) {
   uint32_t head[nhp::kExHeader];
   HIP_CHECK(hipMemcpyAsync(head, plan->d.extract, sizeof(head), hipMemcpyDeviceToHost, plan->stream), "extract copy");
   HIP_CHECK(hipStreamSynchronize(plan->stream), "extract copy");
@@ -426,6 +491,7 @@ int extract_path(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t
   if (status == (uint32_t)(-NHP_EUNREACH))
     return fail(NHP_EUNREACH, "no reached pose in the goal window (or back-tracking lost the path)");
   if (best_ijt) memcpy(best_ijt, head + 2, 3 * sizeof(uint32_t));
+  if (best_index) *best_index = head[7];
   if (goal_value_q10) *goal_value_q10 = head[5];
   if (score_q10) *score_q10 = head[6];
   if (n > NHP_MAX_STEPS_DEVICE || n > cap) return fail(NHP_ECAP, "plan has %u steps, buffer holds %u", n, cap);
@@ -451,6 +517,37 @@ int extract_path(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t
     o.cost_q10 = s[8];
   }
   return ok();
+}
+
+int extract_path_set(nhp_plan* plan, const uint32_t* goals_ijt, const uint32_t* penalty_q10, uint32_t n_goals,
+                     nhp_step* h_steps, uint32_t cap, uint32_t* n_steps, uint32_t* best_index,
+                     uint32_t* goal_value_q10, uint32_t* score_q10) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!plan->has_value) return fail(NHP_ESTATE, "extract_path_set before a sweep");
+  if (!goals_ijt || !penalty_q10 || n_goals < 1 || n_goals > NHP_MAX_GOALS)
+    return fail(NHP_EINVAL, "1..%u goals needed (got %u)", NHP_MAX_GOALS, n_goals);
+  if (cap > 0 && !h_steps) return fail(NHP_EINVAL, "h_steps is NULL");
+  std::vector<uint32_t> g((size_t)n_goals * 4);
+  for (uint32_t k = 0; k < n_goals; k++) {
+    if (goals_ijt[3 * k] >= plan->p.nx || goals_ijt[3 * k + 1] >= plan->p.nx || goals_ijt[3 * k + 2] >= plan->p.ntheta)
+      return fail(NHP_EINVAL, "goal %u outside the grid", k);
+    g[4 * k] = goals_ijt[3 * k];
+    g[4 * k + 1] = goals_ijt[3 * k + 1];
+    g[4 * k + 2] = goals_ijt[3 * k + 2];
+    g[4 * k + 3] = penalty_q10[k];
+  }
+  HIP_CHECK(hipMemcpyAsync(plan->d.goals, g.data(), g.size() * 4, hipMemcpyHostToDevice, plan->stream), "goal upload");
+  nhp::ExArgs x{};
+  x.d = plan->d;
+  x.si = plan->start[0];
+  x.sj = plan->start[1];
+  x.st = plan->start[2];
+  x.n_goals = (int)n_goals;
+  x.n_starts = plan->n_starts;
+  HIP_CHECK(nhp::launch_extract(x, plan->stream), "extract launch");
+  // finish_extract synchronises, so the pageable goal copy has completed
+  return finish_extract(plan, h_steps, cap, n_steps, nullptr, best_index, goal_value_q10, score_q10);
 }
 
 int plan_device_ptrs(const nhp_plan* plan, uint32_t** d_value, uint8_t** d_cspace) {

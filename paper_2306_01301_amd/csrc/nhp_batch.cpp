@@ -189,6 +189,7 @@ int batch_init(nhp_batch* b, nhp_plan* const* plans, const uint32_t* starts_ijt,
           "init launch");
   for (uint32_t k = 0; k < n; k++) {
     plans[k]->has_value = true;
+    plans[k]->n_starts = 0;
     plans[k]->start[0] = starts_ijt[3 * k];
     plans[k]->start[1] = starts_ijt[3 * k + 1];
     plans[k]->start[2] = starts_ijt[3 * k + 2];
@@ -321,7 +322,7 @@ int batch_extract(nhp_batch* b, nhp_plan* const* plans, uint32_t n, const uint32
       return nhp::set_error(NHP_EINVAL, "goal of plans[%u] outside its grid", k);
     if (radius[k] > (uint32_t)nhp::kMaxRadius) return nhp::set_error(NHP_EINVAL, "goal radius of plans[%u] > 31", k);
     args[k] = nhp::ExArgs{p->d, p->start[0], p->start[1], p->start[2], gi, gj, gt, (int)radius[k], w_xy_q10[k],
-                          w_t_q10[k]};
+                          w_t_q10[k], 0, p->n_starts};
   }
   Slot* s;
   const size_t head_words = (size_t)n * nhp::kExHeader;

@@ -50,6 +50,10 @@ struct DevPlan {
   int n_planes_x, n_planes_y;
   int32_t* taps;         // [nt][2 * kMaxTaps] packed (dx & 0xffff) | (dy << 16): side then length
   uint32_t* extract;     // result header + steps
+  nhp_start* starts;     // start set (NHP_MAX_STARTS entries)
+  uint32_t* seeds;       // per start, seed_slots entries of kSeedWords words
+  uint32_t* goals;       // goal set: NHP_MAX_GOALS entries of (i, j, T, penalty)
+  int seed_slots;        // slots per start: max(nx, nt)
   uint32_t ct[6];
   uint32_t turn_lq[6];   // host copy of the (plane-independent) turn edge lengths
   uint8_t schedule[6];
@@ -121,15 +125,20 @@ hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_bloc
 hipError_t launch_init_batch(const InitJob* d_jobs, int n_jobs, size_t max_n4, hipStream_t s);
 
 // extract buffer layout (uint32 words)
-constexpr int kExHeader = 16;  // status, n_steps, best i, j, T, V(best), score, ...
+constexpr int kExHeader = 16;  // status, n_steps, best i, j, T, V(best), score, best goal index, ...
 constexpr int kExStepWords = 9;
+// seed entry: pose index (kNoSeed when unused), value, start index, edges along its maneuver
+constexpr int kSeedWords = 4;
+constexpr uint32_t kNoSeed = 0xFFFFFFFFu;
+
+// Writes the seeds of n starts (init must have set V to INF before).
+hipError_t launch_seed(const DevPlan& d, int n_starts, hipStream_t s);
 
 hipError_t launch_init(const DevPlan& d, uint32_t start_index, hipStream_t s);
 hipError_t launch_force_walls(const DevPlan& d, hipStream_t s);
 hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s);
 hipError_t launch_render(const DevPlan& d, const uint8_t* image, int n_side, int n_len, hipStream_t s);
-hipError_t launch_extract(const DevPlan& d, uint32_t si, uint32_t sj, uint32_t st, uint32_t gi, uint32_t gj,
-                          uint32_t gt, int radius, uint32_t w_xy, uint32_t w_t, hipStream_t s);
+hipError_t launch_extract(const struct ExArgs& x, hipStream_t s);
 
 // Goal search and back-tracking arguments of one plan.
 struct ExArgs {
@@ -137,6 +146,8 @@ struct ExArgs {
   uint32_t si, sj, st, gi, gj, gt;
   int radius;
   uint32_t w_xy, w_t;
+  int n_goals;   // > 0: goal set in d.goals instead of the window
+  int n_starts;  // > 0: the plan ends at a seed of the start set in d.seeds
 };
 hipError_t launch_extract_batch(const ExArgs* d_args, int n, hipStream_t s);
 
@@ -216,6 +227,7 @@ struct nhp_plan {
   // by [first sweep already done by the previous cycle's last pass][last
   // sweep may pair with the next cycle's first].
   hipGraphExec_t cycle[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int n_starts = 0;  // > 0: the value volume was seeded from a start set
   bool graph_failed = false;  // capture unavailable: launch the kernels directly
 };
 

@@ -69,6 +69,9 @@ SIGNATURES = {
     "sweep_resume": (ctypes.c_int, [_vp, _u32]),
     "sweep_one": (ctypes.c_int, [_vp, _u32]),
     "sweep_pass": (ctypes.c_int, [_vp, _i32, _i32]),
+    "sweep_from_set": (ctypes.c_int, [_vp, _vp, _u32, _u32]),
+    "extract_path_set": (ctypes.c_int, [_vp, _vp, _vp, _u32, ctypes.POINTER(NhpStep), _u32, _PU32, _PU32, _PU32,
+                                        _PU32]),
     "schedule_passes": (ctypes.c_int, [_vp, _u32, ctypes.c_uint64, ctypes.c_uint64, _i32, _vp, _vp, _u32, _PU32]),
     "extract_path": (ctypes.c_int, [_vp, _u32, _u32, _u32, _u32, _u32, _u32, ctypes.POINTER(NhpStep), _u32,
                                     _PU32, _PU32, _PU32, _PU32]),
@@ -194,6 +197,14 @@ class Path:
     score: int
 
 
+class NhpStart(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_uint32), ("j", ctypes.c_uint32), ("T", ctypes.c_uint32), ("cost_q10", ctypes.c_uint32),
+                ("maneuver", ctypes.c_int32)]
+
+
+MAX_STARTS, MAX_GOALS = 64, 4096
+
+
 class Planner:
     """One planning problem on one device: owns a workspace tensor and a plan."""
 
@@ -284,6 +295,28 @@ class Planner:
         out = [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_ijt),
                     tuple(int(v) for v in s.to_ijt), int(s.cost_q10)) for s in steps[: n.value]]
         return Path(out, tuple(int(v) for v in best), int(val.value), int(score.value))
+
+    def sweep_from_set(self, starts, n_cycles: int) -> None:
+        """starts: (i, j, T, cost_q10) at rest or (i, j, T, cost_q10, maneuver)
+        with that maneuver in progress."""
+        arr = (NhpStart * len(starts))()
+        for k, st in enumerate(starts):
+            arr[k] = NhpStart(int(st[0]), int(st[1]), int(st[2]), int(st[3]), int(st[4]) if len(st) > 4 else -1)
+        _check(lib().sweep_from_set(self._plan, arr, len(starts), int(n_cycles)), "sweep_from_set")
+
+    def extract_set(self, goals, penalty, cap: int = MAX_STEPS_DEVICE):
+        """Goal set with penalties; returns (Path, index of the chosen goal)."""
+        g = np.ascontiguousarray(np.asarray(goals, np.uint32).reshape(-1))
+        pen = np.ascontiguousarray(np.asarray(penalty, np.uint32))
+        steps = (NhpStep * max(1, cap))()
+        n, k, val, score = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        rc = lib().extract_path_set(self._plan, g.ctypes.data, pen.ctypes.data, len(pen), steps, int(cap),
+                                    ctypes.byref(n), ctypes.byref(k), ctypes.byref(val), ctypes.byref(score))
+        _check(rc, "extract_path_set")
+        out = [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_ijt),
+                    tuple(int(v) for v in s.to_ijt), int(s.cost_q10)) for s in steps[: n.value]]
+        best = tuple(int(v) for v in g[3 * k.value: 3 * k.value + 3])
+        return Path(out, best, int(val.value), int(score.value)), int(k.value)
 
     def tables(self) -> dict:
         L, N = self.nt, self.nx

@@ -1,0 +1,145 @@
+"""GPU parity of start sets and goal sets (Sec. III.A, IX, XII) through the
+C ABI: seeded value volumes after N cycles, goal-set search and
+back-tracking to a start set, against the oracle, bit for bit."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2306_01301_amd import planner as P
+from paper_2306_01301_amd import scenes
+from tests.common import problem_of
+
+pytestmark = pytest.mark.gpu
+
+HARD = 255
+LF, SF, RB, RF, SB, LB = range(6)
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.lib()
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _free(rng, B, count):
+    free = np.argwhere(B != HARD)
+    pick = free[rng.choice(len(free), size=count, replace=False)]
+    return [(int(i), int(j), int(T)) for T, j, i in pick]
+
+
+def _same_steps(a, b):
+    return [(s.maneuver, s.steps, s.frm, s.to, s.cost) for s in a] == [(s.maneuver, s.steps, s.frm, s.to, s.cost)
+                                                                        for s in b]
+
+
+CASES = [(1, 64, 64, 8.0, 4), (2, 96, 72, 6.0, 3), (3, 40, 24, 3.0, 5), (4, 128, 128, 12.0, 2)]
+
+
+@pytest.mark.parametrize("seed,n,nt,R,ncyc", CASES)
+def test_start_sets_match_oracle(seed, n, nt, R, ncyc):
+    rng = np.random.default_rng(seed)
+    sc = scenes.random_small(500 + seed, n=n, nt=nt, R=R, n_rect=max(2, n // 8)).with_(vehicle=(2, 1, 1))
+    prob = problem_of(sc)
+    B = oracle.render(prob, sc.image, *sc.vehicle)
+    poses = _free(rng, B, 8)
+    starts = [(*poses[0], 0, -1), (*poses[1], 2048, RB), (*poses[2], 700, SF), (*poses[3], 5000, LB),
+              (*poses[4], 100, SB), (*poses[5], 9000, -1)]
+    note("start set %s" % ((seed, n, nt, R, ncyc),))
+    p = P.planner_for(sc)
+    p.set_cspace(_dev(B))
+    p.sweep_from_set(starts, ncyc)
+    V = oracle.init_set(prob, B, starts)
+    oracle.cycles(prob, B, V, ncyc)
+    got = p.value_numpy()
+    bad = np.argwhere(got != V)
+    assert bad.size == 0, (bad[:5], got[tuple(bad[0])], V[tuple(bad[0])])
+    # plans from the set: a goal window and a goal set
+    for goal in poses[6:]:
+        try:
+            best, score = oracle.goal_search(prob, B, V, goal, 2, 300, 300)
+        except oracle.OracleError:
+            with pytest.raises(P.NhpError):
+                p.extract(goal, 2, 300, 300)
+            continue
+        want = oracle.backtrack_set(prob, B, V, starts, best)
+        path = p.extract(goal, 2, 300, 300)
+        assert path.best == best and path.score == score
+        assert _same_steps(path.steps, want)
+    goals = _free(rng, B, 40)
+    pens = [int(v) for v in rng.integers(0, 50000, size=len(goals))]
+    try:
+        k, score = oracle.goal_set(prob, B, V, goals, pens)
+    except oracle.OracleError:
+        with pytest.raises(P.NhpError):
+            p.extract_set(goals, pens)
+    else:
+        want = oracle.backtrack_set(prob, B, V, starts, goals[k])
+        path, kk = p.extract_set(goals, pens)
+        assert kk == k and path.score == score and path.best == goals[k]
+        assert _same_steps(path.steps, want)
+    p.close()
+
+
+def test_goal_set_after_single_start():
+    sc = scenes.plain_64()
+    prob = problem_of(sc)
+    B = oracle.render(prob, sc.image, *sc.vehicle)
+    V = oracle.init(prob, B, sc.start)
+    oracle.cycles(prob, B, V, sc.n_cycles)
+    p = P.planner_for(sc)
+    p.set_cspace(_dev(B))
+    p.sweep(sc.start, sc.n_cycles)
+    rng = np.random.default_rng(9)
+    goals = _free(rng, B, 300) + [sc.goal]
+    pens = [int(v) for v in rng.integers(0, 200000, size=len(goals))]
+    k, score = oracle.goal_set(prob, B, V, goals, pens)
+    path, kk = p.extract_set(goals, pens)
+    assert kk == k and path.score == score
+    assert _same_steps(path.steps, oracle.backtrack(prob, B, V, sc.start, goals[k]))
+    # a start set after a plain sweep on the same plan, then a plain sweep again
+    p.sweep_from_set([(*sc.start, 0)], sc.n_cycles)
+    assert np.array_equal(p.value_numpy(), V)
+    p.sweep(sc.start, sc.n_cycles)
+    path2 = p.extract(sc.goal, 0, 0, 0)
+    assert _same_steps(path2.steps, oracle.backtrack(prob, B, V, sc.start, sc.goal))
+    p.close()
+
+
+def test_set_errors():
+    sc = scenes.random_small(7, n=32, nt=16, R=3.0)
+    prob = problem_of(sc)
+    B = oracle.render(prob, sc.image, *sc.vehicle)
+    p = P.planner_for(sc)
+    with pytest.raises(P.NhpError) as e:
+        p.sweep_from_set([(*sc.start, 0)], 1)
+    assert e.value.rc == P.ESTATE
+    p.set_cspace(_dev(B))
+    with pytest.raises(P.NhpError) as e:
+        p.sweep_from_set([(*sc.start, 0), (0, 3, 0, 0)], 1)  # the wall column is hard
+    assert e.value.rc == P.ESTART
+    with pytest.raises(P.NhpError) as e:
+        p.sweep_from_set([(*sc.start, 0, 6)], 1)
+    assert e.value.rc == P.EINVAL
+    with pytest.raises(P.NhpError) as e:
+        p.sweep_from_set([(*sc.start, 0)] * 65, 1)
+    assert e.value.rc == P.EINVAL
+    p.sweep_from_set([(*sc.start, 0)], 1)
+    with pytest.raises(P.NhpError) as e:
+        p.extract_set([(sc.nx, 0, 0)], [0])
+    assert e.value.rc == P.EINVAL
+    p.close()
