@@ -91,6 +91,7 @@ def _L():
         lib.or_backtrack.argtypes = [P(_Problem), vp, vp, i32, i32, i32, vp, vp, i32, vp]
         lib.or_set_threads.argtypes = [i32]
         lib.or_init_set.argtypes = [P(_Problem), vp, vp, vp, i32]
+        lib.or_soft_costs.argtypes = [vp, i32, vp, i32, vp]
         lib.or_goal_set.argtypes = [P(_Problem), vp, vp, vp, vp, i32, vp, vp]
         lib.or_backtrack_set.argtypes = [P(_Problem), vp, vp, vp, i32, vp, vp, i32, vp]
         lib.or_reach.argtypes = [P(_Problem), vp, i32, i32, i32, i32, vp]
@@ -98,7 +99,7 @@ def _L():
         lib.or_reach_backtrack.argtypes = [P(_Problem), vp, vp, vp, vp, i32, vp]
         for name in ("or_tables_export", "or_render_taps", "or_render", "or_init", "or_sweep",
                      "or_cycles", "or_goal_search", "or_backtrack", "or_set_threads", "or_reach",
-                     "or_init_set", "or_goal_set", "or_backtrack_set",
+                     "or_init_set", "or_goal_set", "or_backtrack_set", "or_soft_costs",
                      "or_reach_goal", "or_reach_backtrack"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
@@ -327,3 +328,14 @@ def backtrack_set(prob: Problem, B, V, starts, best, cap: int = 4096) -> List[St
                                  ctypes.addressof(steps), int(cap), ctypes.addressof(n)), "or_backtrack_set")
     return [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_), tuple(int(v) for v in s.to),
                  int(s.cost)) for s in steps[: n.value]]
+
+
+def soft_costs(image: np.ndarray, table) -> np.ndarray:
+    """Codes from the squared distance to the nearest hard pixel (Sec. VI)."""
+    img = np.ascontiguousarray(image, np.uint8)
+    n = img.shape[0]
+    assert img.shape == (n, n)
+    tab = np.ascontiguousarray(np.asarray(table, np.uint8))
+    out = np.empty_like(img)
+    _check(_L().or_soft_costs(_ptr(img), n, _ptr(tab), len(tab), _ptr(out)), "or_soft_costs")
+    return out

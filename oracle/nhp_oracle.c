@@ -22,6 +22,8 @@
  *   cycles     Sec. XVI.A: N cycles of LF, SF, RB, RF, SB, LB.
  *   goal       Sec. IX: best vertex in a window around the goal.
  *   backtrack  Sec. X, eq. (32): reverse Bellman steps back to the start.
+ *   soft costs Sec. VI-VII: obstacle codes from the distance to the nearest
+ *              hard pixel (a squared-distance table).
  *   sets       Sec. III.A, IX, XII: start sets with costs (also inside a
  *              maneuver in progress) and goal sets with penalties.
  *   reach      App. C, Insert 2: reachability by maneuver count (hard
@@ -937,6 +939,53 @@ int or_backtrack_set(const or_problem* p, const uint8_t* B, const uint32_t* V, c
     steps[a] = steps[b];
     steps[b] = t;
   }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* exported: soft obstacle costs from a distance transform (Sec. VI-VII) */
+/* ------------------------------------------------------------------ */
+
+/* The reciprocal of the highest allowed velocity is a function of the
+ * distance to the nearest hard obstacle (Sec. VI).  Here the function is a
+ * table over the squared Euclidean distance in cells: a free pixel gets
+ * table[min(d^2, len - 1)], a hard pixel (code 255) stays 255; with no hard
+ * pixel at all, d^2 counts as unbounded (the last entry).  d^2 is the plain
+ * minimum over hard pixels of dx^2 + dy^2, evaluated through the identity
+ * min over (i', j') = min over i' of ((i - i')^2 + min over j' (j - j')^2),
+ * the inner minimum per column first. */
+int or_soft_costs(const uint8_t* image, int32_t n, const uint8_t* table, int32_t len, uint8_t* out) {
+  if (n < 1 || len < 1) return OR_EINVAL;
+  const int64_t far = (int64_t)1 << 40;
+  int64_t* g = (int64_t*)malloc(sizeof(int64_t) * (size_t)n * n); /* g[j][i]: (j - nearest hard row in column i)^2 */
+  if (!g) return OR_ENOMEM;
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t j = 0; j < n; j++) {
+      int64_t best = far;
+      for (int32_t jj = 0; jj < n; jj++)
+        if (image[(size_t)jj * n + i] == OR_HARD) {
+          int64_t d = (int64_t)(j - jj) * (j - jj);
+          if (d < best) best = d;
+        }
+      g[(size_t)j * n + i] = best;
+    }
+#pragma omp parallel for schedule(static)
+  for (int32_t j = 0; j < n; j++)
+    for (int32_t i = 0; i < n; i++) {
+      size_t x = (size_t)j * n + i;
+      if (image[x] == OR_HARD) {
+        out[x] = OR_HARD;
+        continue;
+      }
+      int64_t best = far;
+      for (int32_t ii = 0; ii < n; ii++) {
+        int64_t d = (int64_t)(i - ii) * (i - ii) + g[(size_t)j * n + ii];
+        if (d < best) best = d;
+      }
+      out[x] = table[best < len - 1 ? best : len - 1];
+    }
+  free(g);
   return OR_OK;
 }
 
