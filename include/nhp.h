@@ -116,6 +116,19 @@ int plan_set_stream(nhp_plan* plan, void* stream);
 int render_cspace(nhp_plan* plan, const uint8_t* d_image, int32_t front, int32_t rear,
                   int32_t half_width);
 
+#define NHP_MAX_SOFT_TABLE 65536u
+
+/* Soft obstacle costs (Sec. VI-VII: the reciprocal of the highest allowed
+ * velocity is a function of the distance to the nearest hard obstacle): for
+ * an nx*nx image of codes (device), d_out[j*nx+i] = 255 where the image is
+ * 255, else h_table[min(d2, table_len - 1)], d2 the squared Euclidean
+ * distance in cells to the nearest pixel coded 255 (unbounded when there is
+ * none).  1 <= table_len <= NHP_MAX_SOFT_TABLE.  d_out and d_image must not
+ * overlap.  Uses the value volume's memory
+ * as scratch (a later extract needs a new sweep); synchronises. */
+int soft_cost_image(nhp_plan* plan, const uint8_t* d_image, uint8_t* d_out, const uint8_t* h_table,
+                    uint32_t table_len);
+
 /* Loads an obstacle volume (nx*nx*ntheta codes, device memory) in place of
  * rendering; the walls at i = 0 and j = 0 are forced hard afterwards. */
 int plan_set_cspace(nhp_plan* plan, const uint8_t* d_cspace);

@@ -1,4 +1,5 @@
-// k_render.hip -- obstacle rendering (Sec. VI) for gfx950.
+// k_render.hip -- obstacle rendering (Sec. VI) for gfx950, and soft
+// obstacle costs from a distance transform of the image (Sec. VI-VII).
 //
 // For every heading plane T the obstacle volume is the maximum of the image
 // codes under the vehicle box, taken separably: a sideways pass over the
@@ -119,7 +120,68 @@ __global__ __launch_bounds__(256) void render_len_batch_kernel(const RenderJob* 
   len_pose(jobs[k], blockIdx.x - jobs[k].first_block, sh);
 }
 
+// ---- soft obstacle costs from a distance transform (Sec. VI-VII) ----
+// Squared Euclidean distance to the nearest hard pixel, split the usual
+// way: per column the squared distance to the nearest hard row, then per
+// row the minimum over columns i' of (i - i')^2 + that column's value.
+
+constexpr uint32_t kFar = 1u << 30;  // no hard pixel in the column
+
+// one thread per column: two passes, down and up
+__global__ __launch_bounds__(256) void soft_cols_kernel(const uint8_t* __restrict__ image, uint32_t* __restrict__ g,
+                                                        int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int last = -1;  // nearest hard row above, -1 for none
+  for (int j = 0; j < n; j++) {
+    if (image[(size_t)j * n + i] == kHard) last = j;
+    g[(size_t)j * n + i] = last < 0 ? kFar : (uint32_t)((j - last) * (j - last));
+  }
+  last = -1;  // nearest hard row below
+  for (int j = n - 1; j >= 0; j--) {
+    if (image[(size_t)j * n + i] == kHard) last = j;
+    if (last >= 0) {
+      const uint32_t d = (uint32_t)((last - j) * (last - j));
+      const size_t x = (size_t)j * n + i;
+      g[x] = d < g[x] ? d : g[x];
+    }
+  }
+}
+
+// one workgroup per row: the row of column values in LDS, a minimum over all
+// columns per pixel, then the table
+__global__ __launch_bounds__(256) void soft_rows_kernel(const uint8_t* __restrict__ image, const uint32_t* __restrict__ g,
+                                                        const uint8_t* __restrict__ table, uint32_t len,
+                                                        uint8_t* __restrict__ out, int n) {
+  __shared__ uint32_t row[1024];
+  const int j = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) row[i] = g[(size_t)j * n + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const size_t x = (size_t)j * n + i;
+    if (image[x] == kHard) {
+      out[x] = (uint8_t)kHard;
+      continue;
+    }
+    uint32_t best = 0xFFFFFFFFu;
+    for (int ii = 0; ii < n; ii++) {
+      const uint32_t d = (uint32_t)((i - ii) * (i - ii)) + row[ii];
+      best = d < best ? d : best;
+    }
+    out[x] = table[best < len - 1 ? best : len - 1];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_soft_costs(const uint8_t* image, uint32_t* g_scratch, const uint8_t* table, uint32_t len,
+                             uint8_t* out, int n, hipStream_t s) {
+  hipLaunchKernelGGL(soft_cols_kernel, dim3((n + 255) / 256), dim3(256), 0, s, image, g_scratch, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(soft_rows_kernel, dim3(n), dim3(256), 0, s, image, g_scratch, table, len, out, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_render(const DevPlan& d, const uint8_t* image, int n_side, int n_len, hipStream_t s) {
   RenderJob r{};

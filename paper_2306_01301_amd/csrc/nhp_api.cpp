@@ -60,6 +60,8 @@ struct Layout {
   size_t V, B, turn_off, skew, edge_len, fwd, family, planes, taps, extract, starts, seeds, goals, total;
 };
 
+static_assert(NHP_MAX_GOALS * 16 >= NHP_MAX_SOFT_TABLE, "the soft-cost table lives in the goal-set buffer");
+
 int seed_slots_of(const nhp_params& p) { return (int)(p.nx > p.ntheta ? p.nx : p.ntheta); }
 
 int check_params(const nhp_params* p) {
@@ -285,6 +287,23 @@ int nhp::upload_taps(nhp_plan* plan, int front, int rear, int half_width) {
 }
 
 extern "C" {
+
+int soft_cost_image(nhp_plan* plan, const uint8_t* d_image, uint8_t* d_out, const uint8_t* h_table,
+                    uint32_t table_len) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!d_image || !d_out || !h_table) return fail(NHP_EINVAL, "image, out or table is NULL");
+  if (table_len < 1 || table_len > NHP_MAX_SOFT_TABLE) return fail(NHP_EINVAL, "table length must be 1..%u", NHP_MAX_SOFT_TABLE);
+  // scratch: the column distances in the value volume's memory, the table in
+  // the goal-set buffer (both are rewritten before their next use)
+  uint8_t* tab = reinterpret_cast<uint8_t*>(plan->d.goals);
+  HIP_CHECK(hipMemcpyAsync(tab, h_table, table_len, hipMemcpyHostToDevice, plan->stream), "table upload");
+  HIP_CHECK(nhp::launch_soft_costs(d_image, plan->d.V, tab, table_len, d_out, (int)plan->p.nx, plan->stream),
+            "soft cost launch");
+  HIP_CHECK(hipStreamSynchronize(plan->stream), "soft costs");  // the table copy is pageable
+  plan->has_value = false;
+  return ok();
+}
 
 int plan_set_cspace(nhp_plan* plan, const uint8_t* d_cspace) {
   int rc = check_plan(plan);

@@ -162,6 +162,9 @@ struct RenderJob {
   int blocks, first_block;
 };
 hipError_t launch_render_batch(const RenderJob* d_jobs, int n_jobs, int total_blocks, hipStream_t s);
+// Soft costs of an n x n image; g_scratch: n^2 words.
+hipError_t launch_soft_costs(const uint8_t* image, uint32_t* g_scratch, const uint8_t* table, uint32_t len,
+                             uint8_t* out, int n, hipStream_t s);
 
 // ---- maneuver-count reachability (App. C) ----
 // Bit volumes: word ((T * N + j) * W + w), W = N / 32, bit t is pose

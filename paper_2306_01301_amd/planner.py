@@ -70,6 +70,7 @@ SIGNATURES = {
     "sweep_one": (ctypes.c_int, [_vp, _u32]),
     "sweep_pass": (ctypes.c_int, [_vp, _i32, _i32]),
     "sweep_from_set": (ctypes.c_int, [_vp, _vp, _u32, _u32]),
+    "soft_cost_image": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
     "extract_path_set": (ctypes.c_int, [_vp, _vp, _vp, _u32, ctypes.POINTER(NhpStep), _u32, _PU32, _PU32, _PU32,
                                         _PU32]),
     "schedule_passes": (ctypes.c_int, [_vp, _u32, ctypes.c_uint64, ctypes.c_uint64, _i32, _vp, _vp, _u32, _PU32]),
@@ -295,6 +296,17 @@ class Planner:
         out = [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_ijt),
                     tuple(int(v) for v in s.to_ijt), int(s.cost_q10)) for s in steps[: n.value]]
         return Path(out, tuple(int(v) for v in best), int(val.value), int(score.value))
+
+    def soft_costs(self, image: torch.Tensor, table) -> torch.Tensor:
+        """Codes from the squared distance to the nearest hard pixel (an nx x
+        nx device image in, a new device image out)."""
+        assert image.dtype == torch.uint8 and image.is_cuda and image.shape == (self.nx, self.nx)
+        image = image.contiguous()
+        out = torch.empty_like(image)
+        tab = np.ascontiguousarray(np.asarray(table, np.uint8))
+        _check(lib().soft_cost_image(self._plan, ctypes.c_void_p(image.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                     tab.ctypes.data, len(tab)), "soft_cost_image")
+        return out
 
     def sweep_from_set(self, starts, n_cycles: int) -> None:
         """starts: (i, j, T, cost_q10) at rest or (i, j, T, cost_q10, maneuver)

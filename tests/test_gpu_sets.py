@@ -143,3 +143,19 @@ def test_set_errors():
         p.extract_set([(sc.nx, 0, 0)], [0])
     assert e.value.rc == P.EINVAL
     p.close()
+
+
+@pytest.mark.parametrize("n,frac,seed", [(16, 0.05, 1), (96, 0.2, 2), (200, 0.1, 3), (512, 0.15, 4), (1024, 0.02, 5)])
+def test_soft_costs_match_oracle(n, frac, seed):
+    rng = np.random.default_rng(seed)
+    img = scenes.mixed_clutter(rng, n, frac) if n >= 32 else np.where(rng.random((n, n)) < frac, HARD, 0).astype(np.uint8)
+    sc = scenes.free_space(n, 8, 2.0, 1)
+    p = P.planner_for(sc)
+    for tab in (np.array([7], np.uint8), (np.arange(65536) % 253).astype(np.uint8),
+                np.clip(np.rint(64 * (4 - np.sqrt(np.arange(17))) / 4), 0, 254).astype(np.uint8)):
+        note("soft costs n=%d table=%d" % (n, len(tab)))
+        got = p.soft_costs(_dev(img), tab).cpu().numpy()
+        assert np.array_equal(got, oracle.soft_costs(img, tab))
+    empty = np.zeros((n, n), np.uint8)
+    assert np.array_equal(p.soft_costs(_dev(empty), np.arange(3, dtype=np.uint8)).cpu().numpy(), np.full((n, n), 2))
+    p.close()
