@@ -276,11 +276,14 @@ __global__ __launch_bounds__(512) void reach_straight_kernel(StraightJob a) {
   __syncthreads();
   const bool fam_x = a.family[T] == 0;
   const bool sf_up = a.fwd[T] > 0;
-  for (int xp = threadIdx.x; xp < N; xp += blockDim.x) {
-    for (int dir = 0; dir < 2; dir++) {
+  // work item: (line, direction), the two directions in different threads
+  for (int item = threadIdx.x; item < 2 * N; item += blockDim.x) {
+    const int xp = item % N, dir = item / N;
+    {
       if (!(dir == 0 ? a.sf_on : a.sb_on)) continue;
       const bool up = (dir == 0) ? sf_up : !sf_up;
       uint32_t v = 1u;
+#pragma unroll 8
       for (int k = 0; k < N; k++) {
         const int c = up ? k : (k == 0 ? 0 : N - k);
         const int o = wrapn(xp + (int)sk[c], N);
@@ -401,7 +404,7 @@ hipError_t launch_reach_cycle(const ReachDev& r, const uint8_t* schedule, int n_
       if (e != hipSuccess) return e;
       attr_set = true;
     }
-    const int threads = r.N < 512 ? r.N : 512;
+    const int threads = 2 * r.N < 512 ? 2 * r.N : 512;
     hipLaunchKernelGGL(reach_straight_kernel, dim3(r.L), dim3(threads), lds, s, j);
     return hipGetLastError();
   }
