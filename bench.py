@@ -152,6 +152,7 @@ def bench_serving(args) -> int:
         srv.close()
         s = serving.latency_summary(res)
         s["rate"] = rate
+        s["one_plan_at_a_time"] = serving.latency_summary(serving.run_fifo(reqs, arr))
         per_rate.append(s)
         print(json.dumps({"rate": rate, **{k: v for k, v in s.items() if k != "rate"}}), file=sys.stderr, flush=True)
     updates = sum(sizing.pose_updates(s.nx, s.nt, s.n_cycles, len(s.schedule)) for s in reqs)

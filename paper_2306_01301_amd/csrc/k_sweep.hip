@@ -700,8 +700,9 @@ hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s) {
 }
 
 template <bool FUSED, bool GUARD>
-hipError_t launch_row_batch_t(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, hipStream_t s) {
-  const dim3 grid(row_grid(total_blocks, 16, P)), block(1024);
+hipError_t launch_row_batch_t(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, int waves,
+                              hipStream_t s) {
+  const dim3 grid(row_grid(total_blocks, waves, P)), block(64 * waves);
   switch (P) {
     case 64:
       if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
@@ -716,17 +717,18 @@ hipError_t launch_row_batch_t(const SweepJob* d_jobs, int n_jobs, int total_bloc
 }
 
 hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool guard,
-                              bool xmajor, hipStream_t s) {
+                              bool xmajor, int waves, hipStream_t s) {
   if (n_jobs == 0) return hipSuccess;
   if (xmajor) {
     hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT>), dim3(total_blocks), dim3(XNT), 0, s, d_jobs, n_jobs);
     return hipGetLastError();
   }
+  if (waves < 1 || waves > 16) return hipErrorInvalidValue;
   if (fused)
-    return guard ? launch_row_batch_t<true, true>(d_jobs, n_jobs, total_blocks, P, s)
-                 : launch_row_batch_t<true, false>(d_jobs, n_jobs, total_blocks, P, s);
-  return guard ? launch_row_batch_t<false, true>(d_jobs, n_jobs, total_blocks, P, s)
-               : launch_row_batch_t<false, false>(d_jobs, n_jobs, total_blocks, P, s);
+    return guard ? launch_row_batch_t<true, true>(d_jobs, n_jobs, total_blocks, P, waves, s)
+                 : launch_row_batch_t<true, false>(d_jobs, n_jobs, total_blocks, P, waves, s);
+  return guard ? launch_row_batch_t<false, true>(d_jobs, n_jobs, total_blocks, P, waves, s)
+               : launch_row_batch_t<false, false>(d_jobs, n_jobs, total_blocks, P, waves, s);
 }
 
 }  // namespace nhp

@@ -198,51 +198,66 @@ int batch_init(nhp_batch* b, nhp_plan* const* plans, const uint32_t* starts_ijt,
   return rc ? rc : nhp::clear_error();
 }
 
-// One pass for each listed plan, all in shared launches: row jobs grouped by
-// section size and by fused or single (one launch per group), x-major jobs in
-// one more launch.
-static int launch_passes(nhp_batch* b, nhp_plan* const* plans, const nhp::Pass* passes, uint32_t n) {
-  static const int kP[4] = {8, 16, 32, 64};
-  constexpr int kRow = 16, kGroups = kRow + 1;  // [guard][fused][P], then x-major
-  std::vector<nhp::SweepJob> group[kGroups];
+// One launch of a batched pass: a group of jobs with the same kernel shape.
+struct Launch {
+  size_t first;  // index of the group's first job in the uploaded table
+  int n_jobs, blocks;
+  int P, fused, guard, waves;  // waves = 0: x-major jobs
+};
+
+// Appends one pass for each listed plan: row jobs grouped by section size,
+// fused or single, guard and wave count (workgroups of exactly the job's
+// waves), x-major jobs in one more group; one launch per group.
+static int add_pass(nhp_plan* const* plans, const nhp::Pass* passes, uint32_t n, std::vector<nhp::SweepJob>& table,
+                    std::vector<Launch>& launches) {
+  struct Group {
+    int P, fused, guard, waves;
+    std::vector<nhp::SweepJob> jobs;
+  };
+  std::vector<Group> groups;
+  auto group_of = [&](int P, int fused, int guard, int waves) -> Group& {
+    for (Group& g : groups)
+      if (g.P == P && g.fused == fused && g.guard == guard && g.waves == waves) return g;
+    groups.push_back(Group{P, fused, guard, waves, {}});
+    return groups.back();
+  };
   for (uint32_t k = 0; k < n; k++) {
     nhp::SweepJob row{}, xm{};
     if (nhp::make_sweep_jobs(plans[k]->d, passes[k], &row, &xm) < 0)
       return nhp::set_error(NHP_EINVAL, "section sizes changed while a batch was being formed");
     if (row.blocks) {
-      int g = 0;
-      while (g < 4 && kP[g] != row.P) g++;
-      if (g == 4) return nhp::set_error(NHP_EINVAL, "a plan has no section size for its curve length");
-      group[8 * (row.L % row.P != 0) + 4 * row.fused + g].push_back(row);
+      if (row.P != 8 && row.P != 16 && row.P != 32 && row.P != 64)
+        return nhp::set_error(NHP_EINVAL, "a plan has no section size for its curve length");
+      group_of(row.P, row.fused, row.L % row.P != 0, (row.L + row.P - 1) / row.P).jobs.push_back(row);
     }
-    if (xm.blocks) group[kRow].push_back(xm);
+    if (xm.blocks) group_of(0, 0, 0, 0).jobs.push_back(xm);
   }
-  size_t total_jobs = 0;
-  for (auto& g : group) total_jobs += g.size();
+  for (Group& g : groups) {
+    Launch l{table.size(), (int)g.jobs.size(), 0, g.P, g.fused, g.guard, g.waves};
+    for (nhp::SweepJob& j : g.jobs) {
+      j.first_block = l.blocks;
+      l.blocks += j.blocks;
+      table.push_back(j);
+    }
+    launches.push_back(l);
+  }
+  return NHP_OK;
+}
+
+// Uploads the job tables of all passes at once, then launches them in order.
+static int run_launches(nhp_batch* b, const std::vector<nhp::SweepJob>& table, const std::vector<Launch>& launches) {
+  if (table.empty()) return NHP_OK;
   Slot* s;
-  int rc = take_slot(b, total_jobs * sizeof(nhp::SweepJob), &s);
+  int rc = take_slot(b, table.size() * sizeof(nhp::SweepJob), &s);
   if (rc) return rc;
-  nhp::SweepJob* h = reinterpret_cast<nhp::SweepJob*>(s->host);
-  size_t off = 0;
-  int blocks[kGroups] = {};
-  size_t first[kGroups];
-  for (int g = 0; g < kGroups; g++) {
-    first[g] = off;
-    for (nhp::SweepJob& j : group[g]) {
-      j.first_block = blocks[g];
-      blocks[g] += j.blocks;
-      h[off++] = j;
-    }
-  }
-  HIP_TRY(hipMemcpyAsync(s->dev, s->host, total_jobs * sizeof(nhp::SweepJob), hipMemcpyHostToDevice, b->stream),
+  memcpy(s->host, table.data(), table.size() * sizeof(nhp::SweepJob));
+  HIP_TRY(hipMemcpyAsync(s->dev, s->host, table.size() * sizeof(nhp::SweepJob), hipMemcpyHostToDevice, b->stream),
           "job upload");
   const nhp::SweepJob* d = reinterpret_cast<const nhp::SweepJob*>(s->dev);
-  for (int g = 0; g < kGroups; g++) {
-    if (group[g].empty()) continue;
-    HIP_TRY(nhp::launch_sweep_batch(d + first[g], (int)group[g].size(), blocks[g], g < kRow ? kP[g % 4] : 0,
-                                    g < kRow && (g & 4), g < kRow && (g & 8), g == kRow, b->stream),
+  for (const Launch& l : launches)
+    HIP_TRY(nhp::launch_sweep_batch(d + l.first, l.n_jobs, l.blocks, l.P, l.fused != 0, l.guard != 0, l.waves == 0,
+                                    l.waves, b->stream),
             "sweep launch");
-  }
   return finish_slot(b, s);
 }
 
@@ -261,6 +276,8 @@ int batch_advance(nhp_batch* b, nhp_plan* const* plans, const uint32_t* steps, c
   }
   std::vector<nhp_plan*> live;
   std::vector<nhp::Pass> now;
+  std::vector<nhp::SweepJob> table;
+  std::vector<Launch> launches;
   for (size_t t = 0; t < most; t++) {
     live.clear();
     now.clear();
@@ -269,10 +286,11 @@ int batch_advance(nhp_batch* b, nhp_plan* const* plans, const uint32_t* steps, c
         live.push_back(plans[k]);
         now.push_back(passes[k][t]);
       }
-    rc = launch_passes(b, live.data(), now.data(), (uint32_t)live.size());
+    rc = add_pass(live.data(), now.data(), (uint32_t)live.size(), table, launches);
     if (rc) return rc;
   }
-  return nhp::clear_error();
+  rc = run_launches(b, table, launches);
+  return rc ? rc : nhp::clear_error();
 }
 
 int batch_step(nhp_batch* b, nhp_plan* const* plans, const uint32_t* steps, uint32_t n) {
@@ -286,7 +304,10 @@ int batch_step(nhp_batch* b, nhp_plan* const* plans, const uint32_t* steps, uint
     if (!p->has_value) return nhp::set_error(NHP_ESTATE, "plans[%u] has no value volume (batch_init first)", k);
     now[k] = nhp::Pass{(int8_t)p->p.schedule[steps[k] % p->p.n_schedule], (int8_t)-1};
   }
-  rc = launch_passes(b, plans, now.data(), n);
+  std::vector<nhp::SweepJob> table;
+  std::vector<Launch> launches;
+  rc = add_pass(plans, now.data(), n, table, launches);
+  if (!rc) rc = run_launches(b, table, launches);
   return rc ? rc : nhp::clear_error();
 }
 

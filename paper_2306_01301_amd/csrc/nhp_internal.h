@@ -119,9 +119,10 @@ struct InitJob {
 int pick_section(int len);
 int set_section_steps(int len, int P);
 int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj);
-// Row jobs of one launch share P, fused and guard (= L % P != 0).
+// Row jobs of one launch share P, fused, guard (= L % P != 0) and their
+// wave count (the workgroup size is 64 waves threads).
 hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool guard,
-                              bool xmajor, hipStream_t s);
+                              bool xmajor, int waves, hipStream_t s);
 hipError_t launch_init_batch(const InitJob* d_jobs, int n_jobs, size_t max_n4, hipStream_t s);
 
 // extract buffer layout (uint32 words)

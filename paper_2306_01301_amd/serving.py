@@ -5,13 +5,16 @@ continuous-batching server.
   entry points (render_cspace, sweep_n_turns, extract_path).
 * `run_batched`: all requests through shared launches (batch_render,
   batch_sweep, batch_extract).
+* `run_fifo`: requests that arrive over time served one at a time in
+  arrival order through the single-plan entry points.
 * `Server`: requests arrive over time (e.g. Poisson); a request is admitted
   when its HBM footprint fits the budget, its map and volumes then stay on
-  the device until it completes.  Every tick advances every admitted plan by
-  a number of sweeps inversely proportional to its size (one batch_advance
-  call, all live plans in shared launches); plans that finish their
-  sweeps are extracted together and release their memory, and requests that
-  arrived meanwhile are admitted at the next tick.
+  the device until it completes.  Small and large plans run in two classes
+  on two streams so their launches overlap; within a class every tick
+  advances every admitted plan by a number of sweeps inversely proportional
+  to its size (one batch_advance call, shared launches); plans that finish
+  their sweeps are extracted together and release their memory, and
+  requests that arrived meanwhile are admitted at the next tick.
 
 Host code only (scheduling and bookkeeping); all planning work runs in the
 HIP library.
@@ -83,6 +86,33 @@ def run_single(scs: Sequence, digests: bool = False) -> List[Result]:
     return out
 
 
+def run_fifo(scs: Sequence, arrivals: Sequence[float]) -> List[Result]:
+    """One plan at a time in arrival order through the single-plan entry
+    points (the baseline for the server: no sharing of launches)."""
+    order = np.argsort(np.asarray(arrivals), kind="stable")
+    results = [Result(sc.name, float(a)) for sc, a in zip(scs, arrivals)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in order:
+        k = int(k)
+        wait = results[k].arrival - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        sc = scs[k]
+        results[k].admitted = time.perf_counter() - t0
+        p = P.planner_for(sc)
+        img = torch.from_numpy(np.ascontiguousarray(sc.image)).cuda()
+        p.render(img, sc.vehicle)
+        p.sweep(sc.start, sc.n_cycles)
+        try:
+            results[k].path = p.extract(sc.goal, sc.goal_radius, sc.w_xy, sc.w_t, cap=512)
+        except P.NhpError as e:
+            results[k].status = e.rc
+        results[k].finished = time.perf_counter() - t0
+        p.close()
+    return results
+
+
 def run_batched(scs: Sequence, digests: bool = False) -> List[Result]:
     """All plans in shared launches (all submitted at t = 0)."""
     torch.cuda.synchronize()
@@ -118,20 +148,36 @@ class _Live:
     planner: P.Planner
     image: torch.Tensor
     total: int
+    cls: int = 0
     done: int = 0
     per_tick: int = 1
     footprint: int = 0
 
 
+LARGE_POSES = 1 << 25  # plans at least this large go to the large class
+LARGE_AT_ONCE = 2      # large plans advanced per tick
+
+
 class Server:
-    """Continuous batching over requests that arrive over time."""
+    """Continuous batching over requests that arrive over time.
+
+    Plans are split into two size classes, each with its own stream and
+    batch, so that the many short passes of small plans run on the GPU at
+    the same time as the long passes of large plans instead of waiting
+    between them.  Every tick advances each live small plan, and the large
+    plans with the least remaining work (at most LARGE_AT_ONCE), by a number
+    of passes inversely proportional to its size within its class (one
+    batch_advance call per class); finished plans are extracted together and
+    release their memory, and requests that arrived meanwhile are admitted at
+    the next tick."""
 
     def __init__(self, hbm_budget: int, max_live: int = 64, rule: str = "formula", digests: bool = False):
         self.budget = int(hbm_budget)
         self.max_live = int(max_live)
         self.rule = rule
         self.digests = digests
-        self.batch = P.Batch(max_live)
+        self.streams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
+        self.batches = [P.Batch(max_live, stream=st) for st in self.streams]
 
     def run(self, scs: Sequence, arrivals: Sequence[float]) -> List[Result]:
         order = np.argsort(np.asarray(arrivals), kind="stable")
@@ -153,34 +199,58 @@ class Server:
                     break
                 pending.pop(0)
                 held += need
-                pl = P.planner_for(sc)
-                img = torch.from_numpy(np.ascontiguousarray(sc.image)).cuda()
-                fresh.append(_Live(k, sc, pl, img, sc.n_cycles * len(sc.schedule), footprint=need))
+                cls = 1 if sc.n_poses >= LARGE_POSES else 0
+                st = self.streams[cls]
+                pl = P.planner_for(sc, stream=st)
+                with torch.cuda.stream(st):
+                    img = torch.from_numpy(np.ascontiguousarray(sc.image)).cuda()
+                fresh.append(_Live(k, sc, pl, img, sc.n_cycles * len(sc.schedule), cls=cls, footprint=need))
                 results[k].admitted = time.perf_counter() - t0
-            if fresh:
-                self.batch.render([f.planner for f in fresh], [f.image for f in fresh], [f.scene.vehicle for f in fresh])
-                self.batch.init([f.planner for f in fresh], [f.scene.start for f in fresh])
-                live.extend(fresh)
+            for cls in (0, 1):
+                new = [f for f in fresh if f.cls == cls]
+                if new:
+                    b = self.batches[cls]
+                    b.render([f.planner for f in new], [f.image for f in new], [f.scene.vehicle for f in new])
+                    b.init([f.planner for f in new], [f.scene.start for f in new])
+            live.extend(fresh)
             if not live:
                 # idle until the next arrival
                 wait = results[pending[0]].arrival - (time.perf_counter() - t0)
                 if wait > 0:
                     time.sleep(min(wait, 0.01))
                 continue
-            # sweeps per tick: inversely proportional to the plan's size
-            biggest = max(l.scene.n_poses for l in live)
-            for l in live:
-                l.per_tick = max(1, min(l.total - l.done, int(round(biggest / l.scene.n_poses))))
-            self.batch.advance([l.planner for l in live], [l.done for l in live], [l.per_tick for l in live])
-            for l in live:
-                l.done += l.per_tick
-            finished = [l for l in live if l.done >= l.total]
-            if finished:
-                paths = self.batch.extract([l.planner for l in finished], [l.scene.goal for l in finished],
-                                           [l.scene.goal_radius for l in finished], [l.scene.w_xy for l in finished],
-                                           [l.scene.w_t for l in finished])
+            finished: List[_Live] = []
+            for cls in (0, 1):
+                mine = [l for l in live if l.cls == cls]
+                if cls == 1:
+                    # large plans: the ones with the least remaining work first
+                    # (shortest remaining work keeps the mean latency low), a
+                    # few at a time so they do not slow each other down
+                    mine.sort(key=lambda l: (l.total - l.done) * l.scene.n_poses)
+                    mine = mine[:LARGE_AT_ONCE]
+                if not mine:
+                    continue
+                # passes per tick: inversely proportional to the plan's size;
+                # a tick ends on a pass boundary so that turn pairs stay fused
+                biggest = max(l.scene.n_poses for l in mine)
+                for l in mine:
+                    want = max(1, int(round(biggest / l.scene.n_poses)))
+                    passes = P.schedule_passes(l.scene.schedule, l.done, l.total - l.done)[:want]
+                    l.per_tick = sum(1 if b < 0 else 2 for _, b in passes)
+                self.batches[cls].advance([l.planner for l in mine], [l.done for l in mine],
+                                          [l.per_tick for l in mine])
+                for l in mine:
+                    l.done += l.per_tick
+                finished += [l for l in mine if l.done >= l.total]
+            for cls in (0, 1):
+                done = [l for l in finished if l.cls == cls]
+                if not done:
+                    continue
+                paths = self.batches[cls].extract([l.planner for l in done], [l.scene.goal for l in done],
+                                                  [l.scene.goal_radius for l in done], [l.scene.w_xy for l in done],
+                                                  [l.scene.w_t for l in done])
                 t = time.perf_counter() - t0
-                for l, path in zip(finished, paths):
+                for l, path in zip(done, paths):
                     r = results[l.k]
                     r.finished = t
                     if isinstance(path, int):
@@ -191,11 +261,12 @@ class Server:
                         r.value_digest = _digest(l.planner)
                     l.planner.close()
                     held -= l.footprint
-                live = [l for l in live if l.done < l.total]
+            live = [l for l in live if l.done < l.total]
         return results
 
     def close(self) -> None:
-        self.batch.close()
+        for b in self.batches:
+            b.close()
 
 
 def latency_summary(results: Sequence[Result]) -> dict:
