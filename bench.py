@@ -37,9 +37,9 @@ BYTES_PER_UPDATE = 9  # read V (4 B) + read obstacle code (1 B) + write V (4 B),
 TURNS = (0, 2, 3, 5)   # LF, RB, RF, LB
 # pass kinds: the kernels one pass of each kind launches
 PASS_KINDS = {
-    "fused_turn": "row_sweep_kernel<32, true, false> (two turn maneuvers on shared circles in one pass)",
-    "turn": "row_sweep_kernel<32, false, false> (one turn maneuver)",
-    "straight": "row_sweep_kernel<32, false, false> (y-major planes) + xmajor_sweep_kernel<32, 256> (x-major planes)",
+    "fused_turn": "row_sweep_kernel<32, true, false, true> (two turn maneuvers on shared circles in one pass)",
+    "turn": "row_sweep_kernel<32, false, false, true> (one turn maneuver)",
+    "straight": "row_sweep_kernel<32, false, false, true> (y-major planes) + xmajor_sweep_kernel<32, 256> (x-major planes)",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweeps_maze_512.json")
 

@@ -63,6 +63,43 @@ __device__ __forceinline__ uint32_t wrap_col(uint32_t i, int N) {
   return j < i ? j : i;
 }
 
+// Index of the pose at column (x + shift) mod N of the row starting at pose
+// rb (a multiple of N).  For a power-of-two N the geometry table holds
+// g = rb | shift, and the pose is g + x with the carry out of the column
+// bits dropped: the low bits of g + x spliced onto the high bits of g
+// (one bitfield insert).
+template <bool POW2>
+__device__ __forceinline__ uint32_t row_cell(uint32_t g, uint32_t x, uint32_t shift, int N) {
+  if (POW2) {
+    const uint32_t m = (uint32_t)N - 1u;
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "s"(m), "v"(g + x), "v"(g));  // (sum & m) | (g & ~m)
+    return r;
+  }
+  return g + wrap_col(x + shift, N);
+}
+
+// Structured buffer access to the row kernels' volumes: the record index is
+// the pose index for both the 4-byte values and the 1-byte codes, so one
+// per-lane index addresses both (the hardware applies the record size), and
+// indices at or past the record count read 0 and drop stores instead of
+// touching memory.
+__device__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset, uint32_t soffset,
+                                    int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.i32");
+__device__ uint8_t buffer_load_u8(__amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset, uint32_t soffset,
+                                  int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.i8");
+__device__ void buffer_store_u32(uint32_t v, __amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset,
+                                 uint32_t soffset, int aux) __asm("llvm.amdgcn.struct.ptr.buffer.store.i32");
+constexpr int kBufferWord3 = 0x00020000;  // descriptor word 3 for untyped access on gfx9-family GPUs
+
+struct RowBuffers {
+  __amdgpu_buffer_rsrc_t V, B;
+};
+__device__ __forceinline__ RowBuffers row_buffers(const SweepJob& a) {
+  return {__builtin_amdgcn_make_buffer_rsrc(a.V, (short)4, (int)a.n_poses, kBufferWord3),
+          __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.B), (short)1, (int)a.n_poses, kBufferWord3)};
+}
+
 // Workgroup index spread over the 8 XCDs so that consecutive tiles (which
 // share row segments at their edges) land on the same XCD and its L2.
 __device__ __forceinline__ int xcd_tile(int b, int n) {
@@ -104,6 +141,7 @@ struct RowShared {
   uint32_t wlut[256];      // edge weight by obstacle code (INF for hard)
   uint32_t wlut2[256];     // the same for the second maneuver
   uint32_t row_base[1024]; // per step: index of the first pose of the row it reads
+                           // (power-of-two N: OR the column offset below)
   uint16_t shift[1024];    // per step: column offset of curve x' (reduced mod N)
 };
 
@@ -111,12 +149,12 @@ struct RowShared {
 // GUARD: the curve length is not a multiple of P, so the last section has
 // fewer than P real steps and the steps past the curve are skipped (without
 // it every section is full and the loops carry no conditions).
-template <int P, bool FUSED, bool GUARD>
-__device__ __forceinline__ void scan_section(const SweepJob& a, RowShared& sh, uint32_t (&u)[P], uint32_t (&code)[P],
-                                             int n_real, int S, int wave, int lane, bool cyclic, bool busy,
-                                             bool active, int xp, int first, int N) {
+template <int P, bool FUSED, bool GUARD, bool POW2>
+__device__ __forceinline__ void scan_section(const SweepJob& a, const RowBuffers& buf, RowShared& sh,
+                                             uint32_t (&u)[P], uint32_t (&code)[P], int n_real, int S, int wave,
+                                             int lane, bool cyclic, bool active, int xp, int first, int N) {
   uint32_t packed[FUSED ? P / 4 : 1];
-  if (busy) {
+  {
     // weights replace the codes; compose the section into (D, C):
     // min(C + w, u + ct + w) = min(C, u + ct) + w (saturating add is monotone).
     // A fused pair keeps the codes, packed four to a register, for the
@@ -126,7 +164,10 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, RowShared& sh, u
     if (FUSED) {
 #pragma unroll
       for (int q = 0; q < P / 4; q++)
+      {
         packed[q] = code[4 * q] | (code[4 * q + 1] << 8) | (code[4 * q + 2] << 16) | (code[4 * q + 3] << 24);
+        asm volatile("" : "+v"(packed[q]));  // keep the packed form (not P live codes)
+      }
     }
 #pragma unroll
     for (int k = 0; k < P; k++) code[k] = sh.wlut[code[k]];
@@ -141,7 +182,7 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, RowShared& sh, u
     sh.aggC[wave][lane] = C;
   }
   __syncthreads();
-  if (busy) {
+  {
     uint32_t v = section_carry(sh.aggD, sh.aggC, S, wave, lane, cyclic);
     // replay: a hard pose has weight INF, and w >> 31 (arithmetic) is then
     // all ones, which forces its output to INF
@@ -170,29 +211,27 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, RowShared& sh, u
   }
   if (FUSED) {
     __syncthreads();
-    if (busy) {
-      uint32_t v = section_carry<true>(sh.aggD2, sh.aggC2, S, wave, lane, cyclic);
+    uint32_t v = section_carry<true>(sh.aggD2, sh.aggC2, S, wave, lane, cyclic);
 #pragma unroll
-      for (int k = P - 1; k >= 0; k--) {
-        if (!GUARD || k < n_real) {
-          const uint32_t w = code[k];
-          const uint32_t uu = u[k];
-          u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
-          v = sadd(umin(v, sadd(uu, a.ct2)), w);
-        }
+    for (int k = P - 1; k >= 0; k--) {
+      if (!GUARD || k < n_real) {
+        const uint32_t w = code[k];
+        const uint32_t uu = u[k];
+        u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+        v = sadd(umin(v, sadd(uu, a.ct2)), w);
       }
     }
   }
-  if (busy) {
-    // recompute the column of every step rather than keeping P of them live
-    int xs = xp;
-    asm volatile("" : "+v"(xs));
-    if (active) {
+  // recompute the pose of every step rather than keeping P of them live
+  int xs = xp;
+  asm volatile("" : "+v"(xs));
+  if (active) {
 #pragma unroll
-      for (int k = 0; k < P; k++) {
-        if (!GUARD || k < n_real) {
-          st_value(a.V, sh.row_base[first + k] + wrap_col((uint32_t)xs + sh.shift[first + k], N), u[k]);
-        }
+    for (int k = 0; k < P; k++) {
+      if (!GUARD || k < n_real) {
+        buffer_store_u32(u[k], buf.V,
+                         row_cell<POW2>(sh.row_base[first + k], (uint32_t)xs, POW2 ? 0u : sh.shift[first + k], N), 0,
+                         0, 0);
       }
     }
   }
@@ -205,18 +244,22 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, RowShared& sh, u
 // FUSED (turns): after the first maneuver the second one, on the same curves
 // in the opposite direction, runs on the values still held in registers, so
 // the pair costs one read and one write per pose.
-template <int P, bool FUSED, bool GUARD>
+// The workgroup has exactly one wave per section (64 S threads: the
+// launchers size it so); a workgroup of another size skips the tile.
+// POW2: N is a power of two.
+template <int P, bool FUSED, bool GUARD, bool POW2>
 __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowShared& sh) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int N = a.N, L = a.L;
   const bool cyclic = a.cyclic != 0;
-  const int S = (L + P - 1) / P;  // sections of this job (the workgroup may hold more waves)
-  const bool busy = wave < S;
+  const int S = (L + P - 1) / P;  // sections of this job
+  if ((int)blockDim.x != 64 * S) return;  // uniform over the workgroup
   const int tx = tile % a.tiles_x;
   const int outer = tile / a.tiles_x;  // y' (turns) or plane slot (straights)
   const int xp = tx * 64 + lane;
   const bool active = xp < N;
+  const RowBuffers buf = row_buffers(a);
 
   int T0 = 0;
   uint32_t Lq = a.lq;
@@ -249,8 +292,13 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
       shift += (shift < 0) ? N : 0;
       row = c;
     }
-    sh.row_base[s] = ((uint32_t)T * (uint32_t)N + (uint32_t)row) * (uint32_t)N;
-    sh.shift[s] = (uint16_t)shift;
+    const uint32_t rb = ((uint32_t)T * (uint32_t)N + (uint32_t)row) * (uint32_t)N;
+    if (POW2) {
+      sh.row_base[s] = rb | (uint32_t)shift;
+    } else {
+      sh.row_base[s] = rb;
+      sh.shift[s] = (uint16_t)shift;
+    }
   }
   __syncthreads();  // weight table and geometry ready
 
@@ -260,8 +308,7 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
   // identity maps that touch no memory.
   const int n_real = (L - wave * P) < P ? (L - wave * P) : P;  // real steps of this wave
   const int first = wave * P;
-
-  if (busy) {
+  {
     // Load this wave's section of the 64 curves.  Lanes past the grid edge
     // read a valid cell, so the loads carry no branch; lanes are independent
     // curves, so an idle lane's values are never stored.
@@ -271,12 +318,12 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
       // full sections need no clamp, so the geometry reads take constant
       // offsets from one address
       const int s = (!GUARD || first + k < L) ? first + k : L - 1;
-      const uint32_t cell = sh.row_base[s] + wrap_col((uint32_t)xl + sh.shift[s], N);
-      u[k] = ld_value(a.V, cell);
-      code[k] = a.B[cell];
+      const uint32_t cell = row_cell<POW2>(sh.row_base[s], (uint32_t)xl, POW2 ? 0u : sh.shift[s], N);
+      u[k] = buffer_load_u32(buf.V, cell, 0, 0, 0);
+      code[k] = buffer_load_u8(buf.B, cell, 0, 0, 0);
     }
   }
-  scan_section<P, FUSED, GUARD>(a, sh, u, code, n_real, S, wave, lane, cyclic, busy, active, xp, first, N);
+  scan_section<P, FUSED, GUARD, POW2>(a, buf, sh, u, code, n_real, S, wave, lane, cyclic, active, xp, first, N);
 }
 
 // x-major straights (|tan| <= 1): line x' visits (c, x' + B(c)), so lines
@@ -434,16 +481,16 @@ __device__ __forceinline__ int find_job(const SweepJob* __restrict__ jobs, int n
 // tile's loads are issued, and no workgroup launch separates them.  The
 // barrier keeps the LDS tables of the previous tile until every wave is done
 // with them.
-template <int P, bool FUSED, bool GUARD>
+template <int P, bool FUSED, bool GUARD, bool POW2>
 __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepJob job) {
   __shared__ RowShared sh;
   for (int b = blockIdx.x; b < job.blocks; b += gridDim.x) {
     __syncthreads();
-    row_sweep_tile<P, FUSED, GUARD>(job, xcd_tile(b, job.blocks), sh);
+    row_sweep_tile<P, FUSED, GUARD, POW2>(job, xcd_tile(b, job.blocks), sh);
   }
 }
 
-template <int P, bool FUSED, bool GUARD>
+template <int P, bool FUSED, bool GUARD, bool POW2>
 __global__ __launch_bounds__(1024) void row_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs,
                                                                  int total_blocks) {
   __shared__ RowShared sh;
@@ -452,7 +499,7 @@ __global__ __launch_bounds__(1024) void row_sweep_batch_kernel(const SweepJob* _
     const int t = xcd_tile(b, total_blocks);
     const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
     const SweepJob job = jobs[j];
-    row_sweep_tile<P, FUSED, GUARD>(job, t - job.first_block, sh);
+    row_sweep_tile<P, FUSED, GUARD, POW2>(job, t - job.first_block, sh);
   }
 }
 
@@ -591,6 +638,7 @@ int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj) 
   j.V = d.V;
   j.B = d.B;
   j.N = N;
+  j.n_poses = (uint32_t)N * (uint32_t)N * (uint32_t)L;
   j.ct = d.ct[mu];
   j.tiles_x = tiles_x;
   int n = 0;
@@ -636,27 +684,34 @@ int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj) 
   return n;
 }
 
-template <bool FUSED, bool GUARD>
+template <bool FUSED, bool GUARD, bool POW2>
 hipError_t launch_row_job_t(const SweepJob& j, hipStream_t s) {
   const int waves = (j.L + j.P - 1) / j.P;
   const dim3 grid(row_grid(j.blocks, waves, j.P)), block(64 * waves);
   switch (j.P) {
     case 64:
       if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
-      hipLaunchKernelGGL((row_sweep_kernel<64, false, GUARD>), grid, block, 0, s, j);
+      hipLaunchKernelGGL((row_sweep_kernel<64, false, GUARD, POW2>), grid, block, 0, s, j);
       break;
-    case 32: hipLaunchKernelGGL((row_sweep_kernel<32, FUSED, GUARD>), grid, block, 0, s, j); break;
-    case 16: hipLaunchKernelGGL((row_sweep_kernel<16, FUSED, GUARD>), grid, block, 0, s, j); break;
-    case 8: hipLaunchKernelGGL((row_sweep_kernel<8, FUSED, GUARD>), grid, block, 0, s, j); break;
+    case 32: hipLaunchKernelGGL((row_sweep_kernel<32, FUSED, GUARD, POW2>), grid, block, 0, s, j); break;
+    case 16: hipLaunchKernelGGL((row_sweep_kernel<16, FUSED, GUARD, POW2>), grid, block, 0, s, j); break;
+    case 8: hipLaunchKernelGGL((row_sweep_kernel<8, FUSED, GUARD, POW2>), grid, block, 0, s, j); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+template <bool FUSED, bool GUARD>
+hipError_t launch_row_job_g(const SweepJob& j, hipStream_t s) {
+  return is_pow2(j.N) ? launch_row_job_t<FUSED, GUARD, true>(j, s) : launch_row_job_t<FUSED, GUARD, false>(j, s);
+}
+
 hipError_t launch_row_job(const SweepJob& j, hipStream_t s) {
   const bool guard = j.L % j.P != 0;
-  if (j.fused) return guard ? launch_row_job_t<true, true>(j, s) : launch_row_job_t<true, false>(j, s);
-  return guard ? launch_row_job_t<false, true>(j, s) : launch_row_job_t<false, false>(j, s);
+  if (j.fused) return guard ? launch_row_job_g<true, true>(j, s) : launch_row_job_g<true, false>(j, s);
+  return guard ? launch_row_job_g<false, true>(j, s) : launch_row_job_g<false, false>(j, s);
 }
 
 hipError_t launch_init(const DevPlan& d, uint32_t start_index, hipStream_t s) {
@@ -699,25 +754,42 @@ hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s) {
   return hipSuccess;
 }
 
-template <bool FUSED, bool GUARD>
+template <bool FUSED, bool GUARD, bool POW2>
 hipError_t launch_row_batch_t(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, int waves,
                               hipStream_t s) {
   const dim3 grid(row_grid(total_blocks, waves, P)), block(64 * waves);
   switch (P) {
     case 64:
       if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
-      hipLaunchKernelGGL((row_sweep_batch_kernel<64, false, GUARD>), grid, block, 0, s, d_jobs, n_jobs, total_blocks);
+      hipLaunchKernelGGL((row_sweep_batch_kernel<64, false, GUARD, POW2>), grid, block, 0, s, d_jobs, n_jobs,
+                         total_blocks);
       break;
-    case 32: hipLaunchKernelGGL((row_sweep_batch_kernel<32, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs, total_blocks); break;
-    case 16: hipLaunchKernelGGL((row_sweep_batch_kernel<16, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs, total_blocks); break;
-    case 8: hipLaunchKernelGGL((row_sweep_batch_kernel<8, FUSED, GUARD>), grid, block, 0, s, d_jobs, n_jobs, total_blocks); break;
+    case 32:
+      hipLaunchKernelGGL((row_sweep_batch_kernel<32, FUSED, GUARD, POW2>), grid, block, 0, s, d_jobs, n_jobs,
+                         total_blocks);
+      break;
+    case 16:
+      hipLaunchKernelGGL((row_sweep_batch_kernel<16, FUSED, GUARD, POW2>), grid, block, 0, s, d_jobs, n_jobs,
+                         total_blocks);
+      break;
+    case 8:
+      hipLaunchKernelGGL((row_sweep_batch_kernel<8, FUSED, GUARD, POW2>), grid, block, 0, s, d_jobs, n_jobs,
+                         total_blocks);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+template <bool FUSED, bool GUARD>
+hipError_t launch_row_batch_g(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool pow2, int waves,
+                              hipStream_t s) {
+  return pow2 ? launch_row_batch_t<FUSED, GUARD, true>(d_jobs, n_jobs, total_blocks, P, waves, s)
+              : launch_row_batch_t<FUSED, GUARD, false>(d_jobs, n_jobs, total_blocks, P, waves, s);
+}
+
 hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool guard,
-                              bool xmajor, int waves, hipStream_t s) {
+                              bool pow2, bool xmajor, int waves, hipStream_t s) {
   if (n_jobs == 0) return hipSuccess;
   if (xmajor) {
     hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT>), dim3(total_blocks), dim3(XNT), 0, s, d_jobs, n_jobs);
@@ -725,10 +797,10 @@ hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_bloc
   }
   if (waves < 1 || waves > 16) return hipErrorInvalidValue;
   if (fused)
-    return guard ? launch_row_batch_t<true, true>(d_jobs, n_jobs, total_blocks, P, waves, s)
-                 : launch_row_batch_t<true, false>(d_jobs, n_jobs, total_blocks, P, waves, s);
-  return guard ? launch_row_batch_t<false, true>(d_jobs, n_jobs, total_blocks, P, waves, s)
-               : launch_row_batch_t<false, false>(d_jobs, n_jobs, total_blocks, P, waves, s);
+    return guard ? launch_row_batch_g<true, true>(d_jobs, n_jobs, total_blocks, P, pow2, waves, s)
+                 : launch_row_batch_g<true, false>(d_jobs, n_jobs, total_blocks, P, pow2, waves, s);
+  return guard ? launch_row_batch_g<false, true>(d_jobs, n_jobs, total_blocks, P, pow2, waves, s)
+               : launch_row_batch_g<false, false>(d_jobs, n_jobs, total_blocks, P, pow2, waves, s);
 }
 
 }  // namespace nhp

@@ -202,23 +202,24 @@ int batch_init(nhp_batch* b, nhp_plan* const* plans, const uint32_t* starts_ijt,
 struct Launch {
   size_t first;  // index of the group's first job in the uploaded table
   int n_jobs, blocks;
-  int P, fused, guard, waves;  // waves = 0: x-major jobs
+  int P, fused, guard, pow2, waves;  // waves = 0: x-major jobs
 };
 
 // Appends one pass for each listed plan: row jobs grouped by section size,
-// fused or single, guard and wave count (workgroups of exactly the job's
-// waves), x-major jobs in one more group; one launch per group.
+// fused or single, guard, power-of-two grid side and wave count (workgroups
+// of exactly the job's waves), x-major jobs in one more group; one launch
+// per group.
 static int add_pass(nhp_plan* const* plans, const nhp::Pass* passes, uint32_t n, std::vector<nhp::SweepJob>& table,
                     std::vector<Launch>& launches) {
   struct Group {
-    int P, fused, guard, waves;
+    int P, fused, guard, pow2, waves;
     std::vector<nhp::SweepJob> jobs;
   };
   std::vector<Group> groups;
-  auto group_of = [&](int P, int fused, int guard, int waves) -> Group& {
+  auto group_of = [&](int P, int fused, int guard, int pow2, int waves) -> Group& {
     for (Group& g : groups)
-      if (g.P == P && g.fused == fused && g.guard == guard && g.waves == waves) return g;
-    groups.push_back(Group{P, fused, guard, waves, {}});
+      if (g.P == P && g.fused == fused && g.guard == guard && g.pow2 == pow2 && g.waves == waves) return g;
+    groups.push_back(Group{P, fused, guard, pow2, waves, {}});
     return groups.back();
   };
   for (uint32_t k = 0; k < n; k++) {
@@ -228,12 +229,13 @@ static int add_pass(nhp_plan* const* plans, const nhp::Pass* passes, uint32_t n,
     if (row.blocks) {
       if (row.P != 8 && row.P != 16 && row.P != 32 && row.P != 64)
         return nhp::set_error(NHP_EINVAL, "a plan has no section size for its curve length");
-      group_of(row.P, row.fused, row.L % row.P != 0, (row.L + row.P - 1) / row.P).jobs.push_back(row);
+      group_of(row.P, row.fused, row.L % row.P != 0, (row.N & (row.N - 1)) == 0, (row.L + row.P - 1) / row.P)
+          .jobs.push_back(row);
     }
-    if (xm.blocks) group_of(0, 0, 0, 0).jobs.push_back(xm);
+    if (xm.blocks) group_of(0, 0, 0, 0, 0).jobs.push_back(xm);
   }
   for (Group& g : groups) {
-    Launch l{table.size(), (int)g.jobs.size(), 0, g.P, g.fused, g.guard, g.waves};
+    Launch l{table.size(), (int)g.jobs.size(), 0, g.P, g.fused, g.guard, g.pow2, g.waves};
     for (nhp::SweepJob& j : g.jobs) {
       j.first_block = l.blocks;
       l.blocks += j.blocks;
@@ -255,8 +257,8 @@ static int run_launches(nhp_batch* b, const std::vector<nhp::SweepJob>& table, c
           "job upload");
   const nhp::SweepJob* d = reinterpret_cast<const nhp::SweepJob*>(s->dev);
   for (const Launch& l : launches)
-    HIP_TRY(nhp::launch_sweep_batch(d + l.first, l.n_jobs, l.blocks, l.P, l.fused != 0, l.guard != 0, l.waves == 0,
-                                    l.waves, b->stream),
+    HIP_TRY(nhp::launch_sweep_batch(d + l.first, l.n_jobs, l.blocks, l.P, l.fused != 0, l.guard != 0, l.pow2 != 0,
+                                    l.waves == 0, l.waves, b->stream),
             "sweep launch");
   return finish_slot(b, s);
 }

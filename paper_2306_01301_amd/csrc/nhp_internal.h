@@ -74,6 +74,7 @@ struct SweepJob {
   const uint32_t* edge_len; // straights: this maneuver's edge lengths per plane
   const int32_t* fwd;       // straights: forward signs
   int N, L;                 // grid side, curve length
+  uint32_t n_poses;         // poses of the volume (N N headings)
   int cyclic, dir, mu_forward;
   int tiles_x, blocks, first_block;
   int P;                    // steps per wave (row jobs)
@@ -122,7 +123,7 @@ int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj);
 // Row jobs of one launch share P, fused, guard (= L % P != 0) and their
 // wave count (the workgroup size is 64 waves threads).
 hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool guard,
-                              bool xmajor, int waves, hipStream_t s);
+                              bool pow2, bool xmajor, int waves, hipStream_t s);
 hipError_t launch_init_batch(const InitJob* d_jobs, int n_jobs, size_t max_n4, hipStream_t s);
 
 // extract buffer layout (uint32 words)
