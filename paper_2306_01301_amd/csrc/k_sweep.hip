@@ -328,22 +328,26 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
 
 // x-major straights (|tan| <= 1): line x' visits (c, x' + B(c)), so lines
 // that are neighbours in x' sit in different rows at every step and a lane
-// per line would read a column.  A workgroup of 4 waves owns 64 lines and
-// walks them along c in chunks of Q columns.  Per chunk the cells owned by
-// its lines form a sheared band of at most 64 + Q rows; they are loaded row
-// by row (contiguous segments, each cell exactly once) into an LDS tile, the
-// four waves scan Q/4 columns each for all 64 lines (section composition in
-// LDS, carry from the previous chunk), write the results back into the tile,
-// and the tile is stored row by row.
+// per line would read a column.  A workgroup of NT / 64 waves owns 64 lines
+// and walks them along c in chunks of Q columns.  Per chunk the cells owned
+// by its lines form a sheared band of at most 64 + Q - 1 rows; they are read
+// row by row (contiguous segments, each cell exactly once) and written to an
+// LDS tile indexed by (line, column), the waves scan Q / NW columns each for
+// all 64 lines (section composition in LDS, carry from the previous chunk),
+// write the results back into the tile, and the band is stored row by row.
+// A band cell that no line of the tile owns gets a record index past the
+// end of the plane (its load reads nothing and its store is dropped) and an
+// LDS slot in a spare row, so no lane branches.  The tile is double
+// buffered, so a chunk's stores and the next chunk's loads need no barrier
+// between them.
 template <int Q, int NT>
 struct XShared {
   static constexpr int LINES = 64;
-  static constexpr int NW = NT / 64;  // waves
-  static constexpr int R = LINES + Q;  // rows a chunk can touch (|B(c+1) - B(c)| <= 1)
-  static constexpr int PITCH = Q + 1;  // odd pitch: a column read by 64 lanes hits 64 banks
-  uint32_t tV[R * PITCH];
-  uint8_t tB[R * PITCH];
-  int32_t tS[Q];
+  static constexpr int NW = NT / 64;    // waves
+  static constexpr int PITCH = Q + 1;   // odd pitch: lanes reading one column of 64 lines hit 64 banks
+  static constexpr int SLOTS = (LINES + 1) * PITCH;  // 64 lines and the spare row
+  uint32_t tV[2][SLOTS];
+  uint8_t tB[2][SLOTS];
   uint32_t aggD[NW][64];
   uint32_t aggC[NW][64];
   uint32_t wlut[256];
@@ -354,17 +358,22 @@ template <int Q, int NT>
 __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, XShared<Q, NT>& sh) {
   using X = XShared<Q, NT>;
   constexpr int LINES = X::LINES, PITCH = X::PITCH, NW = X::NW;
-  constexpr int SUB = Q / NW;  // columns per wave
+  constexpr int SUB = Q / NW;   // columns per wave
   constexpr int ROWS = NT / Q;  // band rows per load round
-  constexpr int ITER = (X::R * Q + NT - 1) / NT;
+  constexpr int ITER = (LINES + Q - 1 + ROWS - 1) / ROWS;
   static_assert(NT % Q == 0 && Q % NW == 0, "Q must divide the thread count and split over the waves");
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int N = a.N;
+  const uint32_t NN = (uint32_t)N * (uint32_t)N;
   const int x0 = (tile % a.tiles_x) * LINES;
   const int T = a.planes[tile / a.tiles_x];
-  const uint32_t plane = (uint32_t)T * (uint32_t)N * (uint32_t)N;
+  // this plane's values and codes as record arrays indexed by row * N + column
+  const __amdgpu_buffer_rsrc_t bV =
+      __builtin_amdgcn_make_buffer_rsrc(a.V + (size_t)T * NN, (short)4, (int)NN, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t bB =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.B) + (size_t)T * NN, (short)1, (int)NN, kBufferWord3);
   const uint32_t Lq = a.edge_len[T];
   for (int c = tid; c < 256; c += NT) sh.wlut[c] = weight((uint32_t)c, 256u * Lq + 128u, 4u * Lq);
   const int dir = (a.fwd[T] > 0) == (a.mu_forward != 0);
@@ -373,65 +382,66 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
   __syncthreads();
   const int16_t* sk = sh.skew;
   const int kk = tid % Q;  // column of this thread in the load/store phases
-  const int r0 = tid / Q;  // first row of this thread; rows r0 + it * ROWS
-  const bool line_ok = x0 + lane < N;
+  const int r0 = tid / Q;  // first band row of this thread; rows r0 + it * ROWS
+  const int t_lim = (N - x0) < LINES ? (N - x0) : LINES;  // lines of this tile inside the grid
+  const uint32_t spare = LINES * PITCH + kk;               // LDS slot for cells no line owns
+  constexpr uint32_t kNoRecord = 0xFFFFFFFFu;
 
   uint32_t carry = kInf;  // value carried along line x0 + lane into the chunk
-  for (int k0 = 0; k0 < N; k0 += Q) {
+  int buf = 0;
+  for (int k0 = 0; k0 < N; k0 += Q, buf ^= 1) {
+    uint32_t* tV = sh.tV[buf];
+    uint8_t* tB = sh.tB[buf];
     const int nq = (N - k0) < Q ? (N - k0) : Q;
     const int c_first = dir ? k0 : (N - 1 - k0);
     const int c_last = dir ? (k0 + nq - 1) : (N - 1 - (k0 + nq - 1));
     const int b_first = sk[c_first], b_last = sk[c_last];
     const int bmin = b_first < b_last ? b_first : b_last;
-    const int rows = LINES + (b_first > b_last ? b_first - b_last : b_last - b_first);
-    int rowbase = (x0 + bmin) % N;
-    rowbase += (rowbase < 0) ? N : 0;
-    const int my_c = dir ? (k0 + kk) : (N - 1 - (k0 + kk));
+    // grid row of band row 0, reduced mod N (|B| < N, so x0 + bmin is in (-N, 2N))
+    int band0 = x0 + bmin;
+    band0 += (band0 < 0) ? N : 0;
+    band0 -= (band0 >= N) ? N : 0;
     const bool col_ok = kk < nq;
-    const int my_b = col_ok ? (int)sk[my_c] : 0;
-    if (tid < Q) sh.tS[tid] = my_b;
+    const int my_c = dir ? (k0 + kk) : (N - 1 - (k0 + kk));
+    const int my_b = sk[col_ok ? my_c : c_first];
+    const uint32_t tl = col_ok ? (uint32_t)t_lim : 0u;
 
-    // load the band: every owned cell once, rows as contiguous segments
-    uint32_t lv[ITER], lc[ITER];
-    uint32_t cell[ITER];
-    bool own[ITER];
+    // load the band: band row r holds line t = r + bmin - B(c) of column c
+    int row = band0 + r0;
+    row -= (row >= N) ? N : 0;
+    uint32_t rel = (uint32_t)row * (uint32_t)N + (uint32_t)(col_ok ? my_c : 0);
+    int t = r0 + bmin - my_b;
+    uint32_t lv[ITER], lc[ITER], idx[ITER], slot[ITER];
 #pragma unroll
     for (int it = 0; it < ITER; it++) {
-      const int r = r0 + it * ROWS;
-      const int t = r + bmin - my_b;
-      own[it] = col_ok && r < rows && t >= 0 && t < LINES && x0 + t < N;
-      int row = rowbase + r;
-      row = row >= N ? row % N : row;
-      cell[it] = own[it] ? plane + (uint32_t)row * (uint32_t)N + (uint32_t)my_c : plane;
-      lv[it] = ld_value(a.V, cell[it]);
-      lc[it] = a.B[cell[it]];
+      const bool own = (uint32_t)t < tl;
+      idx[it] = own ? rel : kNoRecord;
+      slot[it] = own ? (uint32_t)(t * PITCH + kk) : spare;
+      lv[it] = buffer_load_u32(bV, idx[it], 0, 0, 0);
+      lc[it] = buffer_load_u8(bB, idx[it], 0, 0, 0);
+      t += ROWS;
+      rel = wrap_col(rel + (uint32_t)(ROWS * N), (int)NN);  // ROWS rows down, wrapping around the plane
     }
 #pragma unroll
     for (int it = 0; it < ITER; it++) {
-      if (own[it]) {
-        const int r = r0 + it * ROWS;
-        sh.tV[r * PITCH + kk] = lv[it];
-        sh.tB[r * PITCH + kk] = (uint8_t)lc[it];
-      }
+      tV[slot[it]] = lv[it];
+      tB[slot[it]] = (uint8_t)lc[it];
     }
     __syncthreads();
 
     // scan: wave w takes columns [w SUB, (w+1) SUB) of the chunk for all 64 lines
+    const int line_slot = lane * PITCH + wave * SUB;
     uint32_t u[SUB], w[SUB];
-    int rr[SUB];
 #pragma unroll
     for (int q = 0; q < SUB; q++) {
-      const int kq = wave * SUB + q;
-      const bool ok = kq < nq;
-      rr[q] = ok ? lane + sh.tS[kq] - bmin : 0;  // in [0, rows) for real columns
-      u[q] = ok ? sh.tV[rr[q] * PITCH + kq] : kInf;
-      w[q] = ok ? sh.wlut[sh.tB[rr[q] * PITCH + kq]] : 0u;
+      const bool ok = wave * SUB + q < nq;  // uniform
+      u[q] = ok ? tV[line_slot + q] : kInf;
+      w[q] = ok ? sh.wlut[tB[line_slot + q]] : 0u;
     }
     uint32_t D = 0, C = kInf;
 #pragma unroll
     for (int q = 0; q < SUB; q++) {
-      const bool ok = wave * SUB + q < nq;
-      C = ok ? sadd(umin(C, sadd(u[q], a.ct)), w[q]) : C;
+      C = sadd(umin(C, sadd(u[q], a.ct)), w[q]);
       D = sadd(D, w[q]);
     }
     sh.aggD[wave][lane] = D;
@@ -441,24 +451,17 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
     for (int s = 0; s < wave; s++) v = umin(sadd(v, sh.aggD[s][lane]), sh.aggC[s][lane]);
 #pragma unroll
     for (int q = 0; q < SUB; q++) {
-      const int kq = wave * SUB + q;
-      if (kq < nq && line_ok) {
-        sh.tV[rr[q] * PITCH + kq] = umin(v, u[q]) | (uint32_t)((int32_t)w[q] >> 31);
+      if (wave * SUB + q < nq) {
+        tV[line_slot + q] = umin(v, u[q]) | (uint32_t)((int32_t)w[q] >> 31);
         v = sadd(umin(v, sadd(u[q], a.ct)), w[q]);
       }
     }
     for (int s = 0; s < NW; s++) carry = umin(sadd(carry, sh.aggD[s][lane]), sh.aggC[s][lane]);
     __syncthreads();
 
-    // store the band back
+    // store the band back (cells no line owns have no record: dropped)
 #pragma unroll
-    for (int it = 0; it < ITER; it++) {
-      if (own[it]) {
-        const int r = r0 + it * ROWS;
-        st_value(a.V, cell[it], sh.tV[r * PITCH + kk]);
-      }
-    }
-    __syncthreads();
+    for (int it = 0; it < ITER; it++) buffer_store_u32(tV[slot[it]], bV, idx[it], 0, 0, 0);
   }
 }
 
@@ -512,10 +515,19 @@ int row_grid(int blocks, int waves, int P) {
   return blocks < cap ? blocks : cap;
 }
 
+// x-major workgroups stay resident too.  A tile's stores read only the LDS
+// band, and the next tile writes its band after the barrier that follows its
+// weight and skew tables, so a wave still storing never sees it overwritten.
 template <int Q, int NT>
 __global__ __launch_bounds__(NT) void xmajor_sweep_kernel(SweepJob job) {
   __shared__ XShared<Q, NT> sh;
-  xmajor_sweep_tile<Q, NT>(job, xcd_tile(blockIdx.x, gridDim.x), sh);
+  for (int b = blockIdx.x; b < job.blocks; b += gridDim.x) xmajor_sweep_tile<Q, NT>(job, xcd_tile(b, job.blocks), sh);
+}
+
+// Resident x-major workgroups: 8 per CU (about what fits at once).
+int xmajor_grid(int blocks) {
+  const int cap = 256 * 8;
+  return blocks < cap ? blocks : cap;
 }
 
 template <int Q, int NT>
@@ -575,8 +587,8 @@ __global__ void walls_kernel(uint8_t* __restrict__ B, int N, int L) {
 
 // x-major chunks of 32 columns, 256 threads per workgroup (64 columns with
 // 512 threads and 32 columns with 512 threads measured slower)
-constexpr int XQ = 32;
-constexpr int XNT = 256;
+constexpr int XQ = 32;   // x-major chunk columns
+constexpr int XNT = 256;  // x-major workgroup threads
 
 }  // namespace
 
@@ -748,7 +760,7 @@ hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   if (xmaj.blocks) {
-    hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT>), dim3(xmaj.blocks), dim3(XNT), 0, s, xmaj);
+    hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT>), dim3(xmajor_grid(xmaj.blocks)), dim3(XNT), 0, s, xmaj);
     return hipGetLastError();
   }
   return hipSuccess;
