@@ -284,12 +284,15 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
   uint32_t n = 0, status = 0;
   const int k = tid + 1;
   int seed_hit = -1;  // seed slot the plan ends at (start sets)
+  // value of the current pose: read once here, then handed on by the thread
+  // that finds the next pose (with the step's cost), so a step waits for one
+  // round of loads only
+  uint32_t vcur = d.V[pose_index(N, ci, cj, cT)];
   for (uint32_t iter = 0;; iter++) {
     if (x.n_starts > 0) {
       // the first seed (start order, then along a maneuver in progress) at
       // this pose whose value is the current value ends the plan
       const uint32_t cur = (uint32_t)pose_index(N, ci, cj, cT);
-      const uint32_t vcur = d.V[cur];
       uint64_t hit = ~0ull;
       const int slots = x.n_starts * d.seed_slots;
       for (int e = tid; e < slots; e += kThreads) {
@@ -307,7 +310,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
     // every step strictly lowers the value (edges cost >= 1), so a plan from
     // a swept volume ends well within the step buffer; the bound only stops
     // a walk over a value volume that no sweep produced
-    if (iter > NHP_MAX_STEPS_DEVICE || d.V[pose_index(N, ci, cj, cT)] == kInf) {
+    if (iter > NHP_MAX_STEPS_DEVICE || vcur == kInf) {
       status = (uint32_t)(-NHP_EUNREACH);
       break;
     }
@@ -348,8 +351,19 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
       break;
     }
     const int pos = (int)((best >> 11) & 7), kb = (int)(best & 2047);
-    const uint32_t cand = (uint32_t)(best >> 14);
     const int mu = d.schedule[pos];
+    if (k == kb) {
+#pragma unroll
+      for (int m = 0; m < 6; m++) {
+        if (m == pos) {
+          red32[0][0] = vq[m];                          // value of the next pose
+          red32[0][1] = sadd(d.ct[mu], w[m]);           // ct + edge sum: the step's cost
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t vnext = red32[0][0], cost = red32[0][1];
+    __syncthreads();  // red32 is reused by the next step's scan
     int pi, pj, pT;
     predecessor(d, mu, ci, cj, cT, kb, &pi, &pj, &pT);
     if (tid == 0 && n < NHP_MAX_STEPS_DEVICE) {
@@ -362,12 +376,13 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
       s[5] = ci;
       s[6] = cj;
       s[7] = cT;
-      s[8] = cand - d.V[pose_index(N, pi, pj, pT)];  // ct + edge sum (no saturation below INF)
+      s[8] = cost;
     }
     n++;
     ci = pi;
     cj = pj;
     cT = pT;
+    vcur = vnext;
   }
   if (seed_hit >= 0 && status == 0) {
     // a seed inside a maneuver in progress: that maneuver is the first step

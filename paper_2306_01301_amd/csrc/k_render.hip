@@ -7,56 +7,68 @@
 // heading samples.  The one-cell walls of Sec. V.C sit in row 0 and column 0
 // of the image before dilation, and the wall poses themselves are forced
 // hard afterwards.  Sample offsets come from the host (one table per plane).
-// The image (N^2 bytes) and a scratch plane stay L2-resident; the volume is
-// written once.  The value volume's memory serves as the scratch volume.
+// The image and a scratch plane stay L2-resident; the volume is written
+// once.  The value volume's memory serves as the scratch volume.
 #include "nhp_internal.h"
 
 namespace nhp {
 namespace {
 
 // Sample offsets arrive reduced modulo N (in [0, N)), so one conditional
-// subtraction wraps a coordinate.
+// subtraction wraps a row.
 __device__ __forceinline__ int wrapn(int v, int N) { return v - ((v >= N) ? N : 0); }
 
 __device__ __forceinline__ int tap_dx(int32_t p) { return (int)(p & 0xffff); }
 __device__ __forceinline__ int tap_dy(int32_t p) { return (int)((uint32_t)p >> 16); }
 
-// Samples of a pass are read 8 at a time with independent loads (the tap
-// count is a run-time value, so a plain loop would serialise them).
-template <bool WALLED>
+// Both passes read rows that are padded to 2N columns (column x holds column
+// x mod N), so a sample at column offset dx in [0, N) of pose column i is
+// column i + dx of the padded row: no per-lane wrap.  The scratch space (the
+// value volume, 4 bytes per pose) holds the padded sideways volume (2 bytes
+// per pose) followed by the padded walled image (2 N^2 bytes).
+__device__ __forceinline__ uint8_t* padded_image(const RenderJob& r) {
+  return r.side + (size_t)2 * r.N * r.N * r.nt;
+}
+
+// Sample offsets are the same for the whole block (one heading plane): each
+// is read once into a scalar register, and the row of a sample (a uniform
+// value) is formed in scalar arithmetic.  Samples are taken 8 at a time with
+// independent loads (the count is a run-time value).
 __device__ __forceinline__ uint32_t max_over(const uint8_t* __restrict__ src, const int32_t* __restrict__ tp, int n,
-                                             int i, int j, int N) {
+                                             uint32_t i, int j, int N) {
+  const uint32_t pitch = 2u * (uint32_t)N;  // a padded plane is below 2^21 bytes
   uint32_t m = 0;
   int g = 0;
   for (; g + 8 <= n; g += 8) {
     uint32_t q[8];
 #pragma unroll
     for (int e = 0; e < 8; e++) {
-      const int32_t t = tp[g + e];
-      const int y = wrapn(j + tap_dy(t), N), x = wrapn(i + tap_dx(t), N);
-      q[e] = src[(size_t)y * N + x];
-      if (WALLED) q[e] = (y == 0 || x == 0) ? kHard : q[e];
+      const int32_t t = __builtin_amdgcn_readfirstlane(tp[g + e]);
+      const uint8_t* row = src + ((uint32_t)wrapn(j + tap_dy(t), N) * pitch + (uint32_t)tap_dx(t));
+      q[e] = row[i];
     }
 #pragma unroll
     for (int e = 0; e < 8; e++) m = q[e] > m ? q[e] : m;
   }
   for (; g < n; g++) {
-    const int32_t t = tp[g];
-    const int y = wrapn(j + tap_dy(t), N), x = wrapn(i + tap_dx(t), N);
-    uint32_t q = src[(size_t)y * N + x];
-    if (WALLED) q = (y == 0 || x == 0) ? kHard : q;
+    const int32_t t = __builtin_amdgcn_readfirstlane(tp[g]);
+    const uint8_t* row = src + ((uint32_t)wrapn(j + tap_dy(t), N) * pitch + (uint32_t)tap_dx(t));
+    const uint32_t q = row[i];
     m = q > m ? q : m;
   }
   return m;
 }
 
-// One render job per plan; a block covers 256 columns of one row of one
-// plane: block -> (plane, row, column tile).
-__device__ __forceinline__ void render_pose(const RenderJob& r, int b, int& T, int& j, int& i) {
+// One render job per plan; a block covers 256 columns of kRenderRows rows of
+// one plane: block -> (plane, row group, column tile).  The plane's sample
+// offsets stay in scalar registers over the rows.
+constexpr int kRenderRows = 16;
+__device__ __forceinline__ void render_pose(const RenderJob& r, int b, int& T, int& j0, int& i) {
   const int tiles = (r.N + 255) >> 8;
+  const int groups = (r.N + kRenderRows - 1) / kRenderRows;
   i = (b % tiles) * 256 + threadIdx.x;
-  j = (b / tiles) % r.N;
-  T = b / (tiles * r.N);
+  j0 = ((b / tiles) % groups) * kRenderRows;
+  T = b / (tiles * groups);
 }
 
 __device__ __forceinline__ int find_render_job(const RenderJob* __restrict__ jobs, int n_jobs, int t) {
@@ -71,53 +83,74 @@ __device__ __forceinline__ int find_render_job(const RenderJob* __restrict__ job
   return lo;
 }
 
-// The block's plane's sample offsets are staged in LDS once per block.
-__device__ __forceinline__ void stage_taps(const int32_t* __restrict__ src, int n, int32_t* sh) {
-  for (int g = threadIdx.x; g < n; g += blockDim.x) sh[g] = src[g];
-  __syncthreads();
+// Padded walled image, block b = row b: row 0 and column 0 (in both copies)
+// are the walls of Sec. V.C.
+__device__ __forceinline__ void pad_row(const RenderJob& r, int b) {
+  const int N = r.N;
+  uint8_t* P = padded_image(r) + (size_t)b * 2 * N;
+  const uint8_t* src = r.image + (size_t)b * N;
+  for (int x = threadIdx.x; x < 2 * N; x += blockDim.x) {
+    const int xm = x < N ? x : x - N;
+    P[x] = (b == 0 || xm == 0) ? (uint8_t)kHard : src[xm];
+  }
 }
 
-// side[T][j][i] = max over sideways samples of the walled image
-__device__ __forceinline__ void side_pose(const RenderJob& r, int b, int32_t* sh) {
-  int T, j, i;
-  render_pose(r, b, T, j, i);
-  stage_taps(r.taps + (size_t)T * 2 * kMaxTaps, r.n_side, sh);
+// side[T][j][i] = max over sideways samples of the walled image, written to
+// both copies of the padded row
+__device__ __forceinline__ void side_pose(const RenderJob& r, int b) {
+  int T, j0, i;
+  render_pose(r, b, T, j0, i);
   if (i >= r.N) return;
-  const uint32_t m = max_over<true>(r.image, sh, r.n_side, i, j, r.N);
-  r.side[((size_t)T * r.N + j) * r.N + i] = (uint8_t)m;
+  const int j1 = (j0 + kRenderRows) < r.N ? (j0 + kRenderRows) : r.N;
+  for (int j = j0; j < j1; j++) {
+    const uint32_t m = max_over(padded_image(r), r.taps + (size_t)T * 2 * kMaxTaps, r.n_side, (uint32_t)i, j, r.N);
+    uint8_t* row = r.side + ((size_t)T * r.N + j) * 2 * r.N;
+    row[i] = (uint8_t)m;
+    row[i + r.N] = (uint8_t)m;
+  }
 }
 
 // B[T][j][i] = max over lengthwise samples of side[T]; walls forced hard
-__device__ __forceinline__ void len_pose(const RenderJob& r, int b, int32_t* sh) {
-  int T, j, i;
-  render_pose(r, b, T, j, i);
-  stage_taps(r.taps + (size_t)T * 2 * kMaxTaps + kMaxTaps, r.n_len, sh);
+__device__ __forceinline__ void len_pose(const RenderJob& r, int b) {
+  int T, j0, i;
+  render_pose(r, b, T, j0, i);
   if (i >= r.N) return;
   const size_t NN = (size_t)r.N * r.N;
-  uint32_t m = max_over<false>(r.side + (size_t)T * NN, sh, r.n_len, i, j, r.N);
-  if (i == 0 || j == 0) m = kHard;
-  r.B[(size_t)T * NN + (size_t)j * r.N + i] = (uint8_t)m;
+  const int j1 = (j0 + kRenderRows) < r.N ? (j0 + kRenderRows) : r.N;
+  for (int j = j0; j < j1; j++) {
+    uint32_t m = max_over(r.side + (size_t)T * 2 * NN, r.taps + (size_t)T * 2 * kMaxTaps + kMaxTaps, r.n_len,
+                          (uint32_t)i, j, r.N);
+    if (i == 0 || j == 0) m = kHard;
+    r.B[(size_t)T * NN + (size_t)j * r.N + i] = (uint8_t)m;
+  }
 }
 
-__global__ __launch_bounds__(256) void render_side_kernel(RenderJob r) {
-  __shared__ int32_t sh[kMaxTaps];
-  side_pose(r, blockIdx.x, sh);
-}
-__global__ __launch_bounds__(256) void render_len_kernel(RenderJob r) {
-  __shared__ int32_t sh[kMaxTaps];
-  len_pose(r, blockIdx.x, sh);
+__global__ __launch_bounds__(256) void pad_image_kernel(RenderJob r) { pad_row(r, blockIdx.x); }
+__global__ __launch_bounds__(256) void render_side_kernel(RenderJob r) { side_pose(r, blockIdx.x); }
+__global__ __launch_bounds__(256) void render_len_kernel(RenderJob r) { len_pose(r, blockIdx.x); }
+
+// batched: the pad blocks of job k are N rows starting at pad_first (a
+// running sum over the jobs); the pass blocks follow first_block
+__global__ __launch_bounds__(256) void pad_image_batch_kernel(const RenderJob* __restrict__ jobs, int n_jobs) {
+  int lo = 0, hi = n_jobs - 1, t = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].pad_first <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  pad_row(jobs[lo], t - jobs[lo].pad_first);
 }
 
 __global__ __launch_bounds__(256) void render_side_batch_kernel(const RenderJob* __restrict__ jobs, int n_jobs) {
-  __shared__ int32_t sh[kMaxTaps];
   const int k = find_render_job(jobs, n_jobs, blockIdx.x);
-  side_pose(jobs[k], blockIdx.x - jobs[k].first_block, sh);
+  side_pose(jobs[k], blockIdx.x - jobs[k].first_block);
 }
 
 __global__ __launch_bounds__(256) void render_len_batch_kernel(const RenderJob* __restrict__ jobs, int n_jobs) {
-  __shared__ int32_t sh[kMaxTaps];
   const int k = find_render_job(jobs, n_jobs, blockIdx.x);
-  len_pose(jobs[k], blockIdx.x - jobs[k].first_block, sh);
+  len_pose(jobs[k], blockIdx.x - jobs[k].first_block);
 }
 
 // ---- soft obstacle costs from a distance transform (Sec. VI-VII) ----
@@ -183,6 +216,8 @@ hipError_t launch_soft_costs(const uint8_t* image, uint32_t* g_scratch, const ui
   return hipGetLastError();
 }
 
+int render_blocks(int N, int nt) { return ((N + 255) / 256) * ((N + kRenderRows - 1) / kRenderRows) * nt; }
+
 hipError_t launch_render(const DevPlan& d, const uint8_t* image, int n_side, int n_len, hipStream_t s) {
   RenderJob r{};
   r.image = image;
@@ -193,18 +228,25 @@ hipError_t launch_render(const DevPlan& d, const uint8_t* image, int n_side, int
   r.nt = d.nt;
   r.n_side = n_side;
   r.n_len = n_len;
-  r.blocks = ((d.nx + 255) / 256) * d.nx * d.nt;
-  hipLaunchKernelGGL(render_side_kernel, dim3(r.blocks), dim3(256), 0, s, r);
+  r.blocks = render_blocks(d.nx, d.nt);
+  hipLaunchKernelGGL(pad_image_kernel, dim3(d.nx), dim3(256), 0, s, r);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(render_side_kernel, dim3(r.blocks), dim3(256), 0, s, r);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(render_len_kernel, dim3(r.blocks), dim3(256), 0, s, r);
   return hipGetLastError();
 }
 
-hipError_t launch_render_batch(const RenderJob* d_jobs, int n_jobs, int total_blocks, hipStream_t s) {
+hipError_t launch_render_batch(const RenderJob* d_jobs, int n_jobs, int total_blocks, int total_pad_rows,
+                               hipStream_t s) {
   if (n_jobs == 0) return hipSuccess;
-  hipLaunchKernelGGL(render_side_batch_kernel, dim3(total_blocks), dim3(256), 0, s, d_jobs, n_jobs);
+  hipLaunchKernelGGL(pad_image_batch_kernel, dim3(total_pad_rows), dim3(256), 0, s, d_jobs, n_jobs);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(render_side_batch_kernel, dim3(total_blocks), dim3(256), 0, s, d_jobs, n_jobs);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(render_len_batch_kernel, dim3(total_blocks), dim3(256), 0, s, d_jobs, n_jobs);
   return hipGetLastError();

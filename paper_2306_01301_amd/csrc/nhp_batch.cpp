@@ -120,7 +120,7 @@ int batch_render(nhp_batch* b, nhp_plan* const* plans, const uint8_t* const* d_i
   if (n == 0) return nhp::clear_error();
   if (!d_images || !boxes_frs) return nhp::set_error(NHP_EINVAL, "images or boxes is NULL");
   std::vector<nhp::RenderJob> jobs(n);
-  int total = 0;
+  int total = 0, pad_rows = 0;
   for (uint32_t k = 0; k < n; k++) {
     nhp_plan* p = plans[k];
     if (!d_images[k]) return nhp::set_error(NHP_EINVAL, "images[%u] is NULL", k);
@@ -135,9 +135,11 @@ int batch_render(nhp_batch* b, nhp_plan* const* plans, const uint8_t* const* d_i
     r.nt = p->d.nt;
     r.n_side = 2 * boxes_frs[3 * k + 2] + 1;
     r.n_len = boxes_frs[3 * k] + boxes_frs[3 * k + 1] + 1;
-    r.blocks = ((r.N + 255) / 256) * r.N * r.nt;
+    r.blocks = nhp::render_blocks(r.N, r.nt);
     r.first_block = total;
     total += r.blocks;
+    r.pad_first = pad_rows;
+    pad_rows += r.N;
   }
   Slot* s;
   rc = take_slot(b, jobs.size() * sizeof(nhp::RenderJob), &s);
@@ -145,7 +147,8 @@ int batch_render(nhp_batch* b, nhp_plan* const* plans, const uint8_t* const* d_i
   memcpy(s->host, jobs.data(), jobs.size() * sizeof(nhp::RenderJob));
   HIP_TRY(hipMemcpyAsync(s->dev, s->host, jobs.size() * sizeof(nhp::RenderJob), hipMemcpyHostToDevice, b->stream),
           "job upload");
-  HIP_TRY(nhp::launch_render_batch(reinterpret_cast<const nhp::RenderJob*>(s->dev), (int)n, total, b->stream),
+  HIP_TRY(nhp::launch_render_batch(reinterpret_cast<const nhp::RenderJob*>(s->dev), (int)n, total, pad_rows,
+                                   b->stream),
           "render launch");
   for (uint32_t k = 0; k < n; k++) {
     plans[k]->has_cspace = true;

@@ -157,13 +157,16 @@ hipError_t launch_extract_batch(const ExArgs* d_args, int n, hipStream_t s);
 // lengthwise pass into B.  Batched launches list several plans.
 struct RenderJob {
   const uint8_t* image;
-  uint8_t* side;
+  uint8_t* side;  // scratch: 2 N^2 nt + 2 N^2 bytes (the value volume's memory)
   uint8_t* B;
   const int32_t* taps;
   int N, nt, n_side, n_len;
   int blocks, first_block;
+  int pad_first;  // batched: first padded-image row block of this job
 };
-hipError_t launch_render_batch(const RenderJob* d_jobs, int n_jobs, int total_blocks, hipStream_t s);
+hipError_t launch_render_batch(const RenderJob* d_jobs, int n_jobs, int total_blocks, int total_pad_rows,
+                               hipStream_t s);
+int render_blocks(int N, int nt);  // workgroups of one plan's render passes
 // Soft costs of an n x n image; g_scratch: n^2 words.
 hipError_t launch_soft_costs(const uint8_t* image, uint32_t* g_scratch, const uint8_t* table, uint32_t len,
                              uint8_t* out, int n, hipStream_t s);
