@@ -1,6 +1,8 @@
 // k_extract.hip -- goal search (Sec. IX) and back-tracking (Sec. X, eq. 32)
-// in one single-workgroup kernel, so the value volume never leaves the
-// device and the serial back-tracking loop pays no launch per step.
+// in one kernel, so the value volume never leaves the device and the serial
+// back-tracking loop pays no launch per step.  A single plan uses one
+// workgroup per scheduled maneuver, joined by a grid-wide barrier per step;
+// a batch uses one workgroup per plan.
 //
 // Back-tracking step ("Bellman iteration in reverse"): for every scheduled
 // maneuver mu, thread t examines the pose p_k, k = t + 1, up the mu-curve
@@ -204,11 +206,50 @@ __global__ __launch_bounds__(kThreads) void seed_kernel(DevPlan d) {
   }
 }
 
-__device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[kWaves], uint64_t* red64) {
+// Grid-wide barrier of the back-tracking workgroups (one per scheduled
+// maneuver): thread 0 counts its workgroup in (a release, after its
+// exchange writes) and polls, a bounded number of times, until `target`
+// workgroups have arrived.  False when it gave up.
+constexpr uint32_t kMaxPolls = 1u << 24;
+__device__ bool group_barrier(uint32_t* counter, uint32_t target, uint32_t* flag) {
+  if (threadIdx.x == 0) {
+    uint32_t ok = 1, polls = 0;
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++polls > kMaxPolls) {
+        ok = 0;
+        break;
+      }
+      if (polls < 4096)
+        __builtin_amdgcn_s_sleep(1);
+      else
+        __builtin_amdgcn_s_sleep(32);
+    }
+    *flag = ok;
+  }
+  __syncthreads();
+  const bool ok = *flag != 0;
+  __syncthreads();
+  return ok;
+}
+
+__device__ __forceinline__ uint32_t load_shared_word(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// GROUP: workgroup g examines the candidates of schedule position g only and
+// the workgroups exchange their best (key, value, step cost) through the
+// words after the step list; every workgroup then takes the same decision.
+// Workgroup 0 writes the result.
+template <bool GROUP>
+__device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[kWaves], uint64_t* red64,
+                                             uint32_t* flag) {
   const DevPlan& d = x.d;
   const int N = d.nx, L = d.nt;
   const int tid = threadIdx.x;
   uint32_t* out = d.extract;
+  const bool writer = !GROUP || blockIdx.x == 0;
+  uint32_t* sync = out + kExHeader + (size_t)NHP_MAX_STEPS_DEVICE * kExStepWords;
 
   int ci, cj, cT;
   if (x.n_goals > 0) {
@@ -224,7 +265,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
     }
     key = block_min_u64(key, red64);
     if (key == ~0ull) {
-      if (tid == 0) {
+      if (tid == 0 && writer) {
         out[0] = (uint32_t)(-NHP_EUNREACH);
         out[1] = 0;
       }
@@ -234,7 +275,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
     ci = (int)g[0];
     cj = (int)g[1];
     cT = (int)g[2];
-    if (tid == 0) {
+    if (tid == 0 && writer) {
       out[2] = ci;
       out[3] = cj;
       out[4] = cT;
@@ -261,7 +302,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
     }
     key = block_min_u64(key, red64);
     if (key == ~0ull) {
-      if (tid == 0) {
+      if (tid == 0 && writer) {
         out[0] = (uint32_t)(-NHP_EUNREACH);
         out[1] = 0;
       }
@@ -270,7 +311,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
     ci = modn((int)x.gi + (int)(key & 63) - r, N);
     cj = modn((int)x.gj + (int)((key >> 6) & 63) - r, N);
     cT = modn((int)x.gt + (int)((key >> 12) & 63) - r, L);
-    if (tid == 0) {
+    if (tid == 0 && writer) {
       out[2] = ci;
       out[3] = cj;
       out[4] = cT;
@@ -314,59 +355,96 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
       status = (uint32_t)(-NHP_EUNREACH);
       break;
     }
-    // candidates k = tid + 1 of every scheduled maneuver: all loads first
-    uint32_t w[6], vq[6];
-    bool ok[6];
+    // candidates k = tid + 1 of every scheduled maneuver (GROUP: of this
+    // workgroup's one): all loads first
+    constexpr int M = GROUP ? 1 : 6;
+    uint32_t w[M], vq[M];
+    bool ok[M];
 #pragma unroll
-    for (int pos = 0; pos < 6; pos++) {
-      w[pos] = kInf;
-      vq[pos] = kInf;
-      ok[pos] = false;
+    for (int m = 0; m < M; m++) {
+      const int pos = GROUP ? (int)blockIdx.x : m;
+      w[m] = kInf;
+      vq[m] = kInf;
+      ok[m] = false;
       if (pos < d.n_schedule) {
         const int mu = d.schedule[pos];
         int pi = 0, pj = 0, pT = 0;
-        ok[pos] = predecessor(d, mu, ci, cj, cT, k, &pi, &pj, &pT);
-        if (ok[pos]) {
+        ok[m] = predecessor(d, mu, ci, cj, cT, k, &pi, &pj, &pT);
+        if (ok[m]) {
           const size_t q = pose_index(N, pi, pj, pT);
-          w[pos] = weight(d.B[q], d.edge_len[(size_t)mu * L + pT]);
-          vq[pos] = d.V[q];
+          w[m] = weight(d.B[q], d.edge_len[(size_t)mu * L + pT]);
+          vq[m] = d.V[q];
         }
       }
     }
-    block_scan_sat<6>(w, red32);  // w[pos] becomes the edge sum E_k
+    block_scan_sat<M>(w, red32);  // w[m] becomes the edge sum E_k
     uint64_t best = ~0ull;
 #pragma unroll
-    for (int pos = 0; pos < 6; pos++) {
+    for (int m = 0; m < M; m++) {
+      const int pos = GROUP ? (int)blockIdx.x : m;
       if (pos < d.n_schedule) {
-        const uint32_t cand = sadd(sadd(vq[pos], d.ct[d.schedule[pos]]), w[pos]);
-        if (ok[pos] && cand != kInf) {
+        const uint32_t cand = sadd(sadd(vq[m], d.ct[d.schedule[pos]]), w[m]);
+        if (ok[m] && cand != kInf) {
           const uint64_t k2 = ((uint64_t)cand << 14) | ((uint64_t)pos << 11) | (uint64_t)k;
           best = k2 < best ? k2 : best;
         }
       }
     }
     best = block_min_u64(best, red64);
+    // the thread holding the best candidate hands on its pose's value and
+    // the step's cost (ct + edge sum)
+    if (best != ~0ull && k == (int)(best & 2047)) {
+      const int bpos = (int)((best >> 11) & 7);
+#pragma unroll
+      for (int m = 0; m < M; m++) {
+        if ((GROUP ? (int)blockIdx.x : m) == bpos) {
+          red32[0][0] = vq[m];
+          red32[0][1] = sadd(d.ct[d.schedule[bpos]], w[m]);
+        }
+      }
+    }
+    __syncthreads();
+    uint32_t vnext = red32[0][0], cost = red32[0][1];
+    __syncthreads();  // red32 is reused by the next step's scan
+    if (GROUP) {
+      // exchange the workgroups' bests (double-buffered by step parity, so a
+      // fast workgroup's next writes never meet a slow one's reads)
+      uint32_t* mine = sync + 1 + ((iter & 1) * 6 + blockIdx.x) * 4;
+      if (tid == 0) {
+        mine[0] = (uint32_t)best;
+        mine[1] = (uint32_t)(best >> 32);
+        mine[2] = vnext;
+        mine[3] = cost;
+      }
+      if (!group_barrier(sync, gridDim.x * (iter + 1), flag)) {
+        status = (uint32_t)(-NHP_EHIP);
+        break;
+      }
+      best = ~0ull;
+      int from = 0;
+      for (int g = 0; g < (int)gridDim.x; g++) {
+        const uint32_t* e = sync + 1 + ((iter & 1) * 6 + g) * 4;
+        const uint64_t kg = (uint64_t)load_shared_word(e) | ((uint64_t)load_shared_word(e + 1) << 32);
+        if (kg < best) {
+          best = kg;
+          from = g;
+        }
+      }
+      if (best != ~0ull) {
+        const uint32_t* e = sync + 1 + ((iter & 1) * 6 + from) * 4;
+        vnext = load_shared_word(e + 2);
+        cost = load_shared_word(e + 3);
+      }
+    }
     if (best == ~0ull) {
       status = (uint32_t)(-NHP_EUNREACH);
       break;
     }
     const int pos = (int)((best >> 11) & 7), kb = (int)(best & 2047);
     const int mu = d.schedule[pos];
-    if (k == kb) {
-#pragma unroll
-      for (int m = 0; m < 6; m++) {
-        if (m == pos) {
-          red32[0][0] = vq[m];                          // value of the next pose
-          red32[0][1] = sadd(d.ct[mu], w[m]);           // ct + edge sum: the step's cost
-        }
-      }
-    }
-    __syncthreads();
-    const uint32_t vnext = red32[0][0], cost = red32[0][1];
-    __syncthreads();  // red32 is reused by the next step's scan
     int pi, pj, pT;
     predecessor(d, mu, ci, cj, cT, kb, &pi, &pj, &pT);
-    if (tid == 0 && n < NHP_MAX_STEPS_DEVICE) {
+    if (tid == 0 && writer && n < NHP_MAX_STEPS_DEVICE) {
       uint32_t* s = out + kExHeader + (size_t)n * kExStepWords;
       s[0] = mu;
       s[1] = kb;
@@ -389,7 +467,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
     const uint32_t* sd = d.seeds + (size_t)seed_hit * kSeedWords;
     const nhp_start st = d.starts[sd[2]];
     if (sd[3] > 0) {
-      if (tid == 0 && n < NHP_MAX_STEPS_DEVICE) {
+      if (tid == 0 && writer && n < NHP_MAX_STEPS_DEVICE) {
         uint32_t* o = out + kExHeader + (size_t)n * kExStepWords;
         o[0] = (uint32_t)st.maneuver;
         o[1] = sd[3];
@@ -404,24 +482,28 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
       n++;
     }
   }
-  if (tid == 0) {
+  if (tid == 0 && writer) {
     out[0] = status;
     out[1] = n;
   }
 }
 
+// one workgroup per scheduled maneuver (see extract_body)
 __global__ __launch_bounds__(kThreads) void extract_kernel(ExArgs x) {
   __shared__ uint32_t red32[6][kWaves];
   __shared__ uint64_t red64[kWaves];
-  extract_body(x, red32, red64);
+  __shared__ uint32_t flag;
+  extract_body<true>(x, red32, red64, &flag);
 }
+
+__global__ void clear_word_kernel(uint32_t* w) { *w = 0; }
 
 // one workgroup per plan
 __global__ __launch_bounds__(kThreads) void extract_batch_kernel(const ExArgs* __restrict__ args) {
   __shared__ uint32_t red32[6][kWaves];
   __shared__ uint64_t red64[kWaves];
   const ExArgs x = args[blockIdx.x];
-  extract_body(x, red32, red64);
+  extract_body<false>(x, red32, red64, nullptr);
 }
 
 // ---- reachability (App. C): goal search and back-tracking on level bits ----
@@ -554,7 +636,14 @@ hipError_t launch_reach_extract(const ReachExArgs& x, hipStream_t s) {
 }
 
 hipError_t launch_extract(const ExArgs& x, hipStream_t s) {
-  hipLaunchKernelGGL(extract_kernel, dim3(1), dim3(kThreads), 0, s, x);
+  if (x.d.n_schedule < 1 || x.d.n_schedule > 6) return hipErrorInvalidValue;
+  // the barrier counter starts at zero (a kernel, not a memset node, so the
+  // call may be captured)
+  hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(1), 0, s,
+                     x.d.extract + kExHeader + (size_t)NHP_MAX_STEPS_DEVICE * kExStepWords);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(extract_kernel, dim3(x.d.n_schedule), dim3(kThreads), 0, s, x);
   return hipGetLastError();
 }
 

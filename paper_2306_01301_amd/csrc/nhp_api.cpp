@@ -103,7 +103,7 @@ Layout layout_of(const nhp_params& p) {
   l.taps = o;
   o = align256(o + (size_t)p.ntheta * 2 * nhp::kMaxTaps * 4);
   l.extract = o;
-  o = align256(o + (nhp::kExHeader + (size_t)NHP_MAX_STEPS_DEVICE * nhp::kExStepWords) * 4);
+  o = align256(o + (nhp::kExHeader + (size_t)NHP_MAX_STEPS_DEVICE * nhp::kExStepWords + nhp::kExSyncWords) * 4);
   l.starts = o;
   o = align256(o + NHP_MAX_STARTS * sizeof(nhp_start));
   l.seeds = o;

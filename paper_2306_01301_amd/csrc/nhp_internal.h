@@ -129,6 +129,9 @@ hipError_t launch_init_batch(const InitJob* d_jobs, int n_jobs, size_t max_n4, h
 // extract buffer layout (uint32 words)
 constexpr int kExHeader = 16;  // status, n_steps, best i, j, T, V(best), score, best goal index, ...
 constexpr int kExStepWords = 9;
+// after the steps: a barrier counter and, per step parity and schedule
+// position, the best candidate key (2 words), its pose's value and the cost
+constexpr int kExSyncWords = 1 + 2 * 6 * 4;
 // seed entry: pose index (kNoSeed when unused), value, start index, edges along its maneuver
 constexpr int kSeedWords = 4;
 constexpr uint32_t kNoSeed = 0xFFFFFFFFu;
