@@ -24,9 +24,9 @@
 //     stores take the neighbour lane's word through a cross-lane permute, so
 //     every store writes one whole aligned word.
 //   * straight lines: one workgroup per heading plane, the plane's level bits,
-//     hard bits and output bits in LDS, one thread per line walking its
-//     poses bit by bit in both directions; reachable poses clear their output
-//     bit with an LDS atomic AND.
+//     hard bits and output bits in LDS with rows along the sweep coordinate
+//     (transposed in 32 x 32 bit blocks for the x-major family), one thread
+//     per 32 lines and direction carrying the lines' bits in one word.
 #include "nhp_internal.h"
 
 namespace nhp {
@@ -258,7 +258,51 @@ struct StraightJob {
 // for the x-major family and (x' + B(c), c) for the y-major one (eq. 23);
 // SF walks c upward when J > 0, SB the other way, and a downward walk starts
 // at c = 0 (in the wall) and continues N - 1, N - 2, ...
-__global__ __launch_bounds__(512) void reach_straight_kernel(StraightJob a) {
+//
+// One workgroup per heading plane.  The plane's level and hard bits go to
+// LDS as a matrix whose row c holds the poses of sweep coordinate c: the
+// plane itself for the y-major family, its transpose for the x-major one
+// (built from 32 x 32 bit blocks).  Then lines x' = 32 g .. 32 g + 31 sit at 32
+// consecutive columns 32 g + B(c) .. of row c, so one thread carries the 32
+// lines' bits in one word: per step it funnels the window out of two words
+// and applies v = (v AND R) OR hard to all 32 lines at once; the lines that
+// are reachable clear their output bits with two LDS atomic ANDs (windows of
+// neighbouring groups share words).  The output matrix is transposed back
+// for the x-major family as it is stored.  (The transposes work on 32 x 32
+// bit blocks in registers: N is a multiple of 32.)
+// Transpose of 32 x 32 bit blocks of a matrix of N rows of W words (bit t
+// of word w of row r is column 32 w + t), 32 lanes per block: lane r loads
+// row r of block (rows 32 X.., word Y), five butterfly stages swap the
+// off-diagonal halves, quarters, ... between lane pairs, and lane r then
+// holds row 32 Y + r, word X of the transpose.  `put` receives (row, word,
+// value).  Every lane of the workgroup must call it (the stages shuffle).
+template <typename Put>
+__device__ __forceinline__ void transpose_blocks(const uint32_t* src, int W, Put put) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+  const int r = lane & 31, n_blocks = W * W, per_round = 2 * n_waves;
+  const int rounds = (n_blocks + per_round - 1) / per_round;
+  for (int it = 0; it < rounds; it++) {
+    const int blk = it * per_round + 2 * wave + (lane >> 5);
+    const bool ok = blk < n_blocks;
+    const int X = ok ? blk / W : 0, Y = ok ? blk % W : 0;
+    uint32_t v = ok ? src[(32 * X + r) * W + Y] : 0u;
+    const uint32_t masks[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+    for (int st = 0; st < 5; st++) {
+      const int j = 16 >> st;
+      const uint32_t other = __shfl_xor(v, j, 64);
+      if ((r & j) == 0) {
+        v ^= (((v >> j) ^ other) & masks[st]) << j;
+      } else {
+        v ^= ((other >> j) ^ v) & masks[st];
+      }
+    }
+    if (ok) put(32 * Y + r, X, v);
+  }
+}
+
+constexpr int kStraightThreads = 256;
+__global__ __launch_bounds__(kStraightThreads) void reach_straight_kernel(StraightJob a) {
   extern __shared__ uint32_t lds[];
   const int N = a.N, W = a.W, NW = N * W;
   uint32_t* Rp = lds;
@@ -267,37 +311,94 @@ __global__ __launch_bounds__(512) void reach_straight_kernel(StraightJob a) {
   int16_t* sk = reinterpret_cast<int16_t*>(lds + 3 * NW);
   const int T = blockIdx.x;
   const size_t plane = (size_t)T * NW;
-  for (int q = threadIdx.x; q < NW; q += blockDim.x) {
-    Rp[q] = a.rin[plane + q];
-    Hp[q] = a.hard[plane + q];
-    Op[q] = ~0u;
-  }
-  for (int c = threadIdx.x; c < N; c += blockDim.x) sk[c] = a.skew[(size_t)T * N + c];
-  __syncthreads();
   const bool fam_x = a.family[T] == 0;
   const bool sf_up = a.fwd[T] > 0;
-  // work item: (line, direction), the two directions in different threads
-  for (int item = threadIdx.x; item < 2 * N; item += blockDim.x) {
-    const int xp = item % N, dir = item / N;
-    {
-      if (!(dir == 0 ? a.sf_on : a.sb_on)) continue;
-      const bool up = (dir == 0) ? sf_up : !sf_up;
-      uint32_t v = 1u;
-#pragma unroll 8
-      for (int k = 0; k < N; k++) {
-        const int c = up ? k : (k == 0 ? 0 : N - k);
-        const int o = wrapn(xp + (int)sk[c], N);
-        const int i = fam_x ? c : o, j = fam_x ? o : c;
-        const int q = j * W + (i >> 5), b = i & 31;
-        v = (v & (Rp[q] >> b)) | (Hp[q] >> b);
-        v &= 1u;
-        if (!v) atomicAnd(&Op[q], ~(1u << b));
+  if (!fam_x) {
+    for (int q = threadIdx.x; q < NW; q += blockDim.x) {
+      Rp[q] = a.rin[plane + q];
+      Hp[q] = a.hard[plane + q];
+    }
+  } else {
+    // row c of the LDS matrices = column c of the plane: each matrix is read
+    // into the output area first, then transposed block by block
+    for (int m = 0; m < 2; m++) {
+      const uint32_t* src = (m == 0 ? a.rin : a.hard) + plane;
+      uint32_t* dst = m == 0 ? Rp : Hp;
+      for (int q = threadIdx.x; q < NW; q += blockDim.x) Op[q] = src[q];
+      __syncthreads();
+      transpose_blocks(Op, W, [&](int row, int w, uint32_t v) { dst[row * W + w] = v; });
+      __syncthreads();
+    }
+  }
+  for (int q = threadIdx.x; q < NW; q += blockDim.x) Op[q] = ~0u;
+  for (int c = threadIdx.x; c < N; c += blockDim.x) sk[c] = a.skew[(size_t)T * N + c];
+  __syncthreads();
+  // Walkers: (group of 32 lines, direction, section of the walk).  A section
+  // maps the entering bits v to (v AND A) OR B (the paper's section value and
+  // distance for bits, App. D); sections compose as (A1 A2, B1 A2 | B2).
+  const int walkers = 2 * W;
+  const int S = blockDim.x / walkers;  // sections per walk (at least 8: W <= 16)
+  const int len = (N + S - 1) / S;
+  uint32_t* aggA = Op + NW + N / 2 + 1;  // after the skew table
+  uint32_t* aggB = aggA + blockDim.x;
+  const int item = threadIdx.x % walkers, sec = threadIdx.x / walkers;
+  const int g = item % W, dir = item / W;
+  const bool on = sec < S && (dir == 0 ? a.sf_on : a.sb_on);
+  const bool up = (dir == 0) ? sf_up : !sf_up;
+  const int k0 = sec * len, k1 = (k0 + len) < N ? (k0 + len) : N;
+  // bits of the 32 lines' poses at walk step k: level window, hard window,
+  // and where they sit (word q of row c at bit r, the rest in word q1)
+  auto window = [&](int k, uint32_t& rw, uint32_t& hw, int& rb, int& q, int& q1, int& r) {
+    const int c = up ? k : (k == 0 ? 0 : N - k);
+    const int col = wrapn(32 * g + (int)sk[c], N);
+    q = col >> 5;
+    r = col & 31;
+    q1 = (q + 1 == W) ? 0 : q + 1;
+    rb = c * W;
+    rw = funnel(Rp[rb + q1], Rp[rb + q], r);
+    hw = funnel(Hp[rb + q1], Hp[rb + q], r);
+  };
+  if (on) {
+    uint32_t A = ~0u, B = 0u;
+    for (int k = k0; k < k1; k++) {
+      uint32_t rw, hw;
+      int rb, q, q1, r;
+      window(k, rw, hw, rb, q, q1, r);
+      A &= rw;
+      B = (B & rw) | hw;
+    }
+    aggA[threadIdx.x] = A;
+    aggB[threadIdx.x] = B;
+  }
+  __syncthreads();
+  if (on) {
+    uint32_t v = ~0u;  // every line enters from the wall unreachable
+    for (int t = 0; t < sec; t++) v = (v & aggA[t * walkers + item]) | aggB[t * walkers + item];
+    for (int k = k0; k < k1; k++) {
+      uint32_t rw, hw;
+      int rb, q, q1, r;
+      window(k, rw, hw, rb, q, q1, r);
+      v = (v & rw) | hw;
+      const uint32_t reach = ~v;  // line t reaches column col + t of row c
+      if (reach) {
+        atomicAnd(&Op[rb + q], ~(reach << r));
+        if (r) atomicAnd(&Op[rb + q1], ~(reach >> (32 - r)));
       }
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < NW; q += blockDim.x)
-    a.rout[plane + q] = a.store ? Op[q] : (a.rout[plane + q] & Op[q]);
+  if (!fam_x) {
+    for (int q = threadIdx.x; q < NW; q += blockDim.x)
+      a.rout[plane + q] = a.store ? Op[q] : (a.rout[plane + q] & Op[q]);
+  } else {
+    // transposed back on the way out
+    uint32_t* out = a.rout + plane;
+    const bool store = a.store != 0;
+    transpose_blocks(Op, W, [&](int row, int w, uint32_t v) {
+      uint32_t* dst = out + (size_t)row * W + w;
+      *dst = store ? v : (*dst & v);
+    });
+  }
 }
 
 template <int P>
@@ -395,17 +496,18 @@ hipError_t launch_reach_cycle(const ReachDev& r, const uint8_t* schedule, int n_
     j.sf_on = sf;
     j.sb_on = sb;
     j.store = store;
-    const size_t lds = (size_t)3 * r.N * r.W * 4 + (size_t)r.N * 2;
+    // three bit matrices, the skew table (rounded up to words), two section
+    // aggregates per thread
+    const size_t lds = ((size_t)3 * r.N * r.W + r.N / 2 + 1 + 2 * kStraightThreads) * 4;
     static bool attr_set = false;
     if (!attr_set) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(reach_straight_kernel),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               3 * kReachMaxN * (kReachMaxN / 32) * 4 + kReachMaxN * 2);
+      const hipError_t e = hipFuncSetAttribute(
+          reinterpret_cast<const void*>(reach_straight_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+          (3 * kReachMaxN * (kReachMaxN / 32) + kReachMaxN / 2 + 1 + 2 * kStraightThreads) * 4);
       if (e != hipSuccess) return e;
       attr_set = true;
     }
-    const int threads = 2 * r.N < 512 ? 2 * r.N : 512;
-    hipLaunchKernelGGL(reach_straight_kernel, dim3(r.L), dim3(threads), lds, s, j);
+    hipLaunchKernelGGL(reach_straight_kernel, dim3(r.L), dim3(kStraightThreads), lds, s, j);
     return hipGetLastError();
   }
   return hipSuccess;

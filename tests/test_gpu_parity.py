@@ -121,6 +121,9 @@ PLAN_CASES = [
     ("clutter200", lambda: scenes.random_instance(np.random.default_rng(8), sides=(200,), thetas=(72,)), 2),
     ("clutter384", lambda: scenes.random_instance(np.random.default_rng(9), sides=(384,), thetas=(128,)), 2),
     ("parking_256", lambda: scenes.parking_256(), None),
+    # short schedules: back-tracking runs one workgroup per scheduled maneuver
+    ("small64_rf", lambda: scenes.random_small(16, n=64, nt=32, R=4.0, n_cycles=3, schedule=(scenes.RF,)), 6),
+    ("small64_lb_sb", lambda: scenes.random_small(14, n=64, nt=40, R=4.0, n_cycles=4, schedule=(scenes.LB, scenes.SB)), 3),
 ]
 
 
