@@ -16,7 +16,8 @@
 //     of the sideways plane staged in LDS); a sample shifted by dx reads two
 //     words and funnels them with one alignbit.
 //   * turn curves: 32 curves per lane (one word of a row of curve origins),
-//     the curve split into S sections of P steps held in registers; both
+//     the curve split into S sections of P steps held in registers (the
+//     shortest sections whose lanes fit a workgroup of 256); both
 //     maneuvers of a circle family (forward and backward along it) run on the
 //     same registers; section results meet in LDS (the three passes of the
 //     Sections technique, App. D, Inserts 6-8, done in one kernel).  A lane's
@@ -139,10 +140,14 @@ struct TurnJob {
 // Lane layout of a workgroup: section sec, row slot rr, word w:
 // thread = (sec * rows + rr) * Wp + w, Wp = W rounded up to a power of two,
 // so the Wp lanes of one (sec, rr) sit together inside one wave.
+// The most threads (sections x rows x words) per workgroup; shorter sections
+// put more lanes to work (at 128 x 128 x 512: 0.30 ms for eight cycles with
+// 256, 0.35 with 128, 0.50 with 64, 0.32 with 512).
+constexpr int kTurnThreads = 256;
 template <int P>
-__global__ __launch_bounds__(256) void reach_turn_kernel(TurnJob a) {
+__global__ __launch_bounds__(kTurnThreads) void reach_turn_kernel(TurnJob a) {
   __shared__ int32_t sox[kReachMaxL], soy[kReachMaxL];
-  __shared__ uint32_t aggD[16][64], aggF[16][64], aggB[16][64];
+  __shared__ uint32_t aggD[kTurnThreads], aggF[kTurnThreads], aggB[kTurnThreads];
   const int tid = threadIdx.x;
   for (int t = tid; t < a.L; t += blockDim.x) {
     sox[t] = a.offx[t];
@@ -186,9 +191,9 @@ __global__ __launch_bounds__(256) void reach_turn_kernel(TurnJob a) {
   }
 #pragma unroll
   for (int k = P - 1; k >= 0; k--) Bk = (Bk & vi[k]) | h[k];
-  aggD[sec][g] = D;
-  aggF[sec][g] = F;
-  aggB[sec][g] = Bk;
+  aggD[sec * G + g] = D;
+  aggF[sec * G + g] = F;
+  aggB[sec * G + g] = Bk;
   __syncthreads();
   // bit entering this section: once around the circle from "unreachable",
   // starting with this section and ending with the one before it
@@ -196,14 +201,14 @@ __global__ __launch_bounds__(256) void reach_turn_kernel(TurnJob a) {
   if (a.fwd_on) {
     int s2 = sec;
     for (int t = 0; t < S; t++) {
-      cf = (cf | aggD[s2][g]) & aggF[s2][g];
+      cf = (cf | aggD[s2 * G + g]) & aggF[s2 * G + g];
       s2 = (s2 + 1 == S) ? 0 : s2 + 1;
     }
   }
   if (a.bwd_on) {
     int s2 = sec;
     for (int t = 0; t < S; t++) {
-      cb = (cb | aggD[s2][g]) & aggB[s2][g];
+      cb = (cb | aggD[s2 * G + g]) & aggB[s2 * G + g];
       s2 = (s2 == 0) ? S - 1 : s2 - 1;
     }
   }
@@ -444,12 +449,14 @@ hipError_t launch_reach_cycle(const ReachDev& r, const uint8_t* schedule, int n_
   int store = 1;
   // turn families: left circles (LF up the headings, LB down), right
   // circles (RB up, RF down), eqs. (25)-(28)
-  int P = 4;
-  while (P < 32 && P * 16 < r.L) P <<= 1;
-  const int S = (r.L + P - 1) / P;
+  // the shortest sections (most parallel lanes) whose lanes fit a workgroup
   int Wp = 1;
   while (Wp < r.W) Wp <<= 1;
-  int rows = 64 / (Wp * S);
+  int P = 4;
+  while (P < 32 && ((r.L + P - 1) / P) * Wp > kTurnThreads) P <<= 1;
+  const int S = (r.L + P - 1) / P;
+  if (S * Wp > kTurnThreads) return hipErrorInvalidValue;  // the plan's checks keep L and N below this
+  int rows = kTurnThreads / (Wp * S);
   if (rows < 1) rows = 1;
   const int threads = S * rows * Wp, blocks = (r.N + rows - 1) / rows;
   for (int fam = 0; fam < 2; fam++) {

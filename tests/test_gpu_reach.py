@@ -2,8 +2,8 @@
 level volume, goal search and back-tracking through the C ABI against the
 oracle, bit for bit.  Sizes cover rows of one word, word counts that are not
 powers of two (idle lanes), curve lengths that are not a multiple of the
-section size, every schedule shape, and the full 128 x 128 x 512, N = 8
-workload."""
+section size, every schedule shape, every turn section length (4 to 32
+steps) and the full 128 x 128 x 512, N = 8 workload."""
 import os
 import sys
 
@@ -57,6 +57,10 @@ CASES = [
     (4, 160, 40, 8.0, (LB, SB, RB), 3, (3, 1, 1)),
     (5, 128, 256, 12.0, (LF, SF, RF, LB), 3, (4, 1, 2)),
     (6, 64, 512, 10.0, (RF,), 2, (2, 1, 1)),
+    # turn sections of 16 and 32 steps (the section length grows with the
+    # words per row so that a workgroup holds a whole row of curves)
+    (7, 256, 512, 10.0, scenes.DEFAULT_SCHEDULE, 2, (3, 1, 1)),
+    (8, 512, 512, 10.0, (LB, SF, RF), 1, (3, 1, 1)),
 ]
 
 
