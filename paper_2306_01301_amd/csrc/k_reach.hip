@@ -443,6 +443,14 @@ hipError_t launch_reach_start(const ReachDev& r, uint32_t start_index, hipStream
   return hipGetLastError();
 }
 
+// The straight kernel's LDS can exceed the default dynamic limit (up to
+// 101 KB at N = 512); set once per device before any launch or capture.
+hipError_t prepare_reach_kernels() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(reach_straight_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (3 * kReachMaxN * (kReachMaxN / 32) + kReachMaxN / 2 + 1 + 2 * kStraightThreads) * 4);
+}
+
 hipError_t launch_reach_cycle(const ReachDev& r, const uint8_t* schedule, int n_schedule, uint32_t m, hipStream_t s) {
   const uint32_t* rin = r.levels + (size_t)m * r.vol_words;
   uint32_t* rout = r.levels + (size_t)(m + 1) * r.vol_words;
@@ -506,14 +514,6 @@ hipError_t launch_reach_cycle(const ReachDev& r, const uint8_t* schedule, int n_
     // three bit matrices, the skew table (rounded up to words), two section
     // aggregates per thread
     const size_t lds = ((size_t)3 * r.N * r.W + r.N / 2 + 1 + 2 * kStraightThreads) * 4;
-    static bool attr_set = false;
-    if (!attr_set) {
-      const hipError_t e = hipFuncSetAttribute(
-          reinterpret_cast<const void*>(reach_straight_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-          (3 * kReachMaxN * (kReachMaxN / 32) + kReachMaxN / 2 + 1 + 2 * kStraightThreads) * 4);
-      if (e != hipSuccess) return e;
-      attr_set = true;
-    }
     hipLaunchKernelGGL(reach_straight_kernel, dim3(r.L), dim3(kStraightThreads), lds, s, j);
     return hipGetLastError();
   }

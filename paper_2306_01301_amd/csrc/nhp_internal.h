@@ -203,6 +203,7 @@ hipError_t launch_reach_pack(const ReachDev& r, const uint8_t* codes, hipStream_
 hipError_t launch_reach_start(const ReachDev& r, uint32_t start_index, hipStream_t s);
 // One cycle: R_{m+1} from R_m with the scheduled maneuvers (at most three
 // launches: left circles, right circles, straight planes).
+hipError_t prepare_reach_kernels();
 hipError_t launch_reach_cycle(const ReachDev& r, const uint8_t* schedule, int n_schedule, uint32_t m, hipStream_t s);
 
 struct ReachExArgs {

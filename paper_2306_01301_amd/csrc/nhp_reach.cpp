@@ -18,6 +18,10 @@ struct nhp_reach {
   nhp::ReachDev r{};
   bool has_hard = false;
   uint32_t n_levels = 0;  // level volumes holding results (0: no sweep yet)
+  // the cycles of the last multi-cycle sweep, captured as one graph
+  hipGraphExec_t cycles = nullptr;
+  uint32_t cycles_n = 0;
+  bool graph_failed = false;
 };
 
 namespace {
@@ -82,6 +86,7 @@ int reach_create(nhp_plan* plan, uint32_t max_cycles, void* d_workspace, size_t 
   int rc = check_reach_params(&plan->p, max_cycles);
   if (rc) return rc;
   const ReachLayout l = reach_layout(plan->p, max_cycles);
+  HIP_TRY(nhp::prepare_reach_kernels(), "reach kernel set-up");
   nhp_reach* r = new (std::nothrow) nhp_reach;
   if (!r) return nhp::set_error(NHP_ENOMEM, "host allocation");
   r->plan = plan;
@@ -127,6 +132,7 @@ int reach_create(nhp_plan* plan, uint32_t max_cycles, void* d_workspace, size_t 
 int reach_destroy(nhp_reach* r) {
   if (!r) return nhp::clear_error();
   (void)hipStreamSynchronize(r->plan->stream);
+  if (r->cycles) (void)hipGraphExecDestroy(r->cycles);
   if (r->own_ws && r->ws) (void)hipFree(r->ws);
   delete r;
   return nhp::clear_error();
@@ -155,6 +161,31 @@ int reach_set_cspace(nhp_reach* r, const uint8_t* d_codes) {
   return nhp::clear_error();
 }
 
+// The launches of n cycles captured once (they depend only on the state's
+// buffers); on any capture failure the eager launches are used from then on.
+static hipGraphExec_t capture_cycles(nhp_reach* r, uint32_t n) {
+  const nhp_params& p = r->plan->p;
+  hipStream_t cs = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    for (uint32_t m = 0; m < n; m++)
+      ok = ok && nhp::launch_reach_cycle(r->r, p.schedule, (int)p.n_schedule, m, cs) == hipSuccess;
+    ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok && g != nullptr;
+  }
+  if (ok) ok = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (!ok) {
+    exec = nullptr;
+    r->graph_failed = true;
+    (void)hipGetLastError();  // clear a sticky capture error
+  }
+  return exec;
+}
+
 int reach_sweep(nhp_reach* r, uint32_t si, uint32_t sj, uint32_t st, uint32_t n_cycles) {
   int rc = check_reach(r);
   if (rc) return rc;
@@ -170,8 +201,17 @@ int reach_sweep(nhp_reach* r, uint32_t si, uint32_t sj, uint32_t st, uint32_t n_
   HIP_TRY(hipStreamSynchronize(s), "start check");
   if ((word >> (idx % 32)) & 1u) return nhp::set_error(NHP_ESTART, "start pose (%u, %u, %u) is in collision", si, sj, st);
   HIP_TRY(nhp::launch_reach_start(r->r, (uint32_t)idx, s), "reach start launch");
-  for (uint32_t m = 0; m < n_cycles; m++)
-    HIP_TRY(nhp::launch_reach_cycle(r->r, p.schedule, (int)p.n_schedule, m, s), "reach cycle launch");
+  if (n_cycles > 1 && !r->graph_failed && (!r->cycles || r->cycles_n != n_cycles)) {
+    if (r->cycles) (void)hipGraphExecDestroy(r->cycles);
+    r->cycles = capture_cycles(r, n_cycles);
+    r->cycles_n = r->cycles ? n_cycles : 0;
+  }
+  if (n_cycles > 1 && r->cycles) {
+    HIP_TRY(hipGraphLaunch(r->cycles, s), "reach cycles graph launch");
+  } else {
+    for (uint32_t m = 0; m < n_cycles; m++)
+      HIP_TRY(nhp::launch_reach_cycle(r->r, p.schedule, (int)p.n_schedule, m, s), "reach cycle launch");
+  }
   r->n_levels = n_cycles + 1;
   return nhp::clear_error();
 }

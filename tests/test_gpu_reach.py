@@ -134,6 +134,18 @@ def test_reach_128_full_size():
     path = rc.extract(sc.goal, 0)
     assert path.best == best and path.level == lv == len(steps)
     assert [(s.maneuver, s.steps, s.frm, s.to) for s in path.steps] == [(s.maneuver, s.steps, s.frm, s.to) for s in steps]
+    # the cycles replay from a captured graph: again from another start, with
+    # eager work and a synchronisation between the replays, then the first again
+    other = (sc.goal[0], sc.goal[1], sc.goal[2])
+    for start in (other, sc.start, other):
+        if B[start[2], start[1], start[0]] == HARD:
+            continue
+        rc.sweep(start, sc.n_cycles)
+        torch.cuda.synchronize()
+        assert np.array_equal(_levels(rc, sc.n_cycles, B.shape), oracle.reach(prob, B, start, sc.n_cycles))
+        rc.sweep(start, 2)  # a two-cycle sweep in between (captured on its own)
+        torch.cuda.synchronize()
+        assert np.array_equal(_levels(rc, 2, B.shape), oracle.reach(prob, B, start, 2))
     rc.close()
     pl.close()
 
