@@ -30,46 +30,50 @@ __device__ __forceinline__ uint8_t* padded_image(const RenderJob& r) {
   return r.side + (size_t)2 * r.N * r.N * r.nt;
 }
 
-// Sample offsets are the same for the whole block (one heading plane): each
-// is read once into a scalar register, and the row of a sample (a uniform
-// value) is formed in scalar arithmetic.  Samples are taken 8 at a time with
-// independent loads (the count is a run-time value).
-__device__ __forceinline__ uint32_t max_over(const uint8_t* __restrict__ src, const int32_t* __restrict__ tp, int n,
-                                             uint32_t i, int j, int N) {
+// A thread renders 4 consecutive poses of a row (N is a multiple of 8).  A
+// sample's 4 bytes at an arbitrary column come from two aligned words
+// funnelled with one byte align, and the maximum runs on the bytes as two
+// pairs of 16-bit lanes (even and odd bytes), so a sample costs two word
+// loads for 4 poses instead of 4 byte loads.  Sample offsets are the same
+// for the whole block (one heading plane): staged in LDS, each is read into
+// a scalar register.  Samples are taken 4 at a time with independent loads
+// (the count is a run-time value).
+typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t window4(const uint8_t* row, uint32_t a) {
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(row + (a & ~3u));
+  return __builtin_amdgcn_alignbyte(w[1], w[0], a & 3u);  // bytes a .. a + 3
+}
+
+__device__ __forceinline__ uint32_t max4_over(const uint8_t* __restrict__ src, const int32_t* tp, int n, uint32_t i0,
+                                              int j, int N) {
   const uint32_t pitch = 2u * (uint32_t)N;  // a padded plane is below 2^21 bytes
-  uint32_t m = 0;
+  ushort2_t me = {0, 0}, mo = {0, 0};
+  auto take = [&](uint32_t win) {
+    me = __builtin_elementwise_max(me, __builtin_bit_cast(ushort2_t, win & 0x00FF00FFu));
+    mo = __builtin_elementwise_max(mo, __builtin_bit_cast(ushort2_t, (win >> 8) & 0x00FF00FFu));
+  };
   int g = 0;
-  for (; g + 8 <= n; g += 8) {
-    uint32_t q[8];
+  for (; g + 4 <= n; g += 4) {
+    uint32_t q[4];
 #pragma unroll
-    for (int e = 0; e < 8; e++) {
+    for (int e = 0; e < 4; e++) {
       const int32_t t = __builtin_amdgcn_readfirstlane(tp[g + e]);
-      const uint8_t* row = src + ((uint32_t)wrapn(j + tap_dy(t), N) * pitch + (uint32_t)tap_dx(t));
-      q[e] = row[i];
+      q[e] = window4(src + __umul24((uint32_t)wrapn(j + tap_dy(t), N), pitch), i0 + (uint32_t)tap_dx(t));
     }
 #pragma unroll
-    for (int e = 0; e < 8; e++) m = q[e] > m ? q[e] : m;
+    for (int e = 0; e < 4; e++) take(q[e]);
   }
   for (; g < n; g++) {
     const int32_t t = __builtin_amdgcn_readfirstlane(tp[g]);
-    const uint8_t* row = src + ((uint32_t)wrapn(j + tap_dy(t), N) * pitch + (uint32_t)tap_dx(t));
-    const uint32_t q = row[i];
-    m = q > m ? q : m;
+    take(window4(src + __umul24((uint32_t)wrapn(j + tap_dy(t), N), pitch), i0 + (uint32_t)tap_dx(t)));
   }
-  return m;
+  return __builtin_bit_cast(uint32_t, me) | (__builtin_bit_cast(uint32_t, mo) << 8);
 }
 
-// One render job per plan; a block covers 256 columns of kRenderRows rows of
-// one plane: block -> (plane, row group, column tile).  The plane's sample
-// offsets stay in scalar registers over the rows.
+// One render job per plan; a block covers kRenderRows rows of one plane:
+// block -> (plane, row group); its threads walk the rows' 4-pose groups.
 constexpr int kRenderRows = 16;
-__device__ __forceinline__ void render_pose(const RenderJob& r, int b, int& T, int& j0, int& i) {
-  const int tiles = (r.N + 255) >> 8;
-  const int groups = (r.N + kRenderRows - 1) / kRenderRows;
-  i = (b % tiles) * 256 + threadIdx.x;
-  j0 = ((b / tiles) % groups) * kRenderRows;
-  T = b / (tiles * groups);
-}
 
 __device__ __forceinline__ int find_render_job(const RenderJob* __restrict__ jobs, int n_jobs, int t) {
   int lo = 0, hi = n_jobs - 1;
@@ -95,39 +99,56 @@ __device__ __forceinline__ void pad_row(const RenderJob& r, int b) {
   }
 }
 
-// side[T][j][i] = max over sideways samples of the walled image, written to
-// both copies of the padded row
-__device__ __forceinline__ void side_pose(const RenderJob& r, int b) {
-  int T, j0, i;
-  render_pose(r, b, T, j0, i);
-  if (i >= r.N) return;
-  const int j1 = (j0 + kRenderRows) < r.N ? (j0 + kRenderRows) : r.N;
-  for (int j = j0; j < j1; j++) {
-    const uint32_t m = max_over(padded_image(r), r.taps + (size_t)T * 2 * kMaxTaps, r.n_side, (uint32_t)i, j, r.N);
-    uint8_t* row = r.side + ((size_t)T * r.N + j) * 2 * r.N;
-    row[i] = (uint8_t)m;
-    row[i + r.N] = (uint8_t)m;
-  }
-}
-
-// B[T][j][i] = max over lengthwise samples of side[T]; walls forced hard
-__device__ __forceinline__ void len_pose(const RenderJob& r, int b) {
-  int T, j0, i;
-  render_pose(r, b, T, j0, i);
-  if (i >= r.N) return;
-  const size_t NN = (size_t)r.N * r.N;
-  const int j1 = (j0 + kRenderRows) < r.N ? (j0 + kRenderRows) : r.N;
-  for (int j = j0; j < j1; j++) {
-    uint32_t m = max_over(r.side + (size_t)T * 2 * NN, r.taps + (size_t)T * 2 * kMaxTaps + kMaxTaps, r.n_len,
-                          (uint32_t)i, j, r.N);
-    if (i == 0 || j == 0) m = kHard;
-    r.B[(size_t)T * NN + (size_t)j * r.N + i] = (uint8_t)m;
+// SIDE: side[T][j][i] = max over sideways samples of the walled image,
+// written to both copies of the padded row.  Otherwise B[T][j][i] = max over
+// lengthwise samples of side[T], walls forced hard.
+template <bool SIDE>
+__device__ __forceinline__ void render_rows(const RenderJob& r, int b, int32_t* tp) {
+  const int N = r.N, G = N / 4;
+  const int groups = (N + kRenderRows - 1) / kRenderRows;
+  const int T = b / groups, j0 = (b % groups) * kRenderRows;
+  const int j1 = (j0 + kRenderRows) < N ? (j0 + kRenderRows) : N;
+  const size_t NN = (size_t)N * N;
+  const int n = SIDE ? r.n_side : r.n_len;
+  // the plane's sample offsets in LDS (global loads of them would be vector
+  // loads: the stores below might alias them)
+  const int32_t* tg = r.taps + (size_t)T * 2 * kMaxTaps + (SIDE ? 0 : kMaxTaps);
+  for (int g = threadIdx.x; g < n; g += blockDim.x) tp[g] = tg[g];
+  __syncthreads();
+  const uint8_t* src = SIDE ? padded_image(r) : r.side + (size_t)T * 2 * NN;
+  // the loop runs the same number of times in every lane, so the sample
+  // offsets stay scalar loads (a lane past the end repeats the last group)
+  const int total = (j1 - j0) * G;
+  for (int base = 0; base < total; base += blockDim.x) {
+    const int item = base + (int)threadIdx.x;
+    const bool valid = item < total;
+    const int it = valid ? item : total - 1;
+    const int j = j0 + it / G;
+    const uint32_t i0 = 4u * (uint32_t)(it % G);
+    uint32_t m = max4_over(src, tp, n, i0, j, N);
+    if (SIDE) {
+      uint8_t* row = r.side + ((size_t)T * N + j) * 2 * N;
+      if (valid) {
+        *reinterpret_cast<uint32_t*>(row + i0) = m;
+        *reinterpret_cast<uint32_t*>(row + i0 + N) = m;
+      }
+    } else {
+      if (j == 0) m = 0xFFFFFFFFu;
+      if (i0 == 0) m |= kHard;
+      if (valid) *reinterpret_cast<uint32_t*>(r.B + (size_t)T * NN + (size_t)j * N + i0) = m;
+    }
   }
 }
 
 __global__ __launch_bounds__(256) void pad_image_kernel(RenderJob r) { pad_row(r, blockIdx.x); }
-__global__ __launch_bounds__(256) void render_side_kernel(RenderJob r) { side_pose(r, blockIdx.x); }
-__global__ __launch_bounds__(256) void render_len_kernel(RenderJob r) { len_pose(r, blockIdx.x); }
+__global__ __launch_bounds__(256) void render_side_kernel(RenderJob r) {
+  __shared__ int32_t tp[kMaxTaps];
+  render_rows<true>(r, blockIdx.x, tp);
+}
+__global__ __launch_bounds__(256) void render_len_kernel(RenderJob r) {
+  __shared__ int32_t tp[kMaxTaps];
+  render_rows<false>(r, blockIdx.x, tp);
+}
 
 // batched: the pad blocks of job k are N rows starting at pad_first (a
 // running sum over the jobs); the pass blocks follow first_block
@@ -145,12 +166,14 @@ __global__ __launch_bounds__(256) void pad_image_batch_kernel(const RenderJob* _
 
 __global__ __launch_bounds__(256) void render_side_batch_kernel(const RenderJob* __restrict__ jobs, int n_jobs) {
   const int k = find_render_job(jobs, n_jobs, blockIdx.x);
-  side_pose(jobs[k], blockIdx.x - jobs[k].first_block);
+  __shared__ int32_t tp[kMaxTaps];
+  render_rows<true>(jobs[k], blockIdx.x - jobs[k].first_block, tp);
 }
 
 __global__ __launch_bounds__(256) void render_len_batch_kernel(const RenderJob* __restrict__ jobs, int n_jobs) {
   const int k = find_render_job(jobs, n_jobs, blockIdx.x);
-  len_pose(jobs[k], blockIdx.x - jobs[k].first_block);
+  __shared__ int32_t tp[kMaxTaps];
+  render_rows<false>(jobs[k], blockIdx.x - jobs[k].first_block, tp);
 }
 
 // ---- soft obstacle costs from a distance transform (Sec. VI-VII) ----
@@ -216,7 +239,7 @@ hipError_t launch_soft_costs(const uint8_t* image, uint32_t* g_scratch, const ui
   return hipGetLastError();
 }
 
-int render_blocks(int N, int nt) { return ((N + 255) / 256) * ((N + kRenderRows - 1) / kRenderRows) * nt; }
+int render_blocks(int N, int nt) { return ((N + kRenderRows - 1) / kRenderRows) * nt; }
 
 hipError_t launch_render(const DevPlan& d, const uint8_t* image, int n_side, int n_len, hipStream_t s) {
   RenderJob r{};
