@@ -155,7 +155,7 @@ class _Live:
 
 
 LARGE_POSES = 1 << 25  # plans at least this large go to the large class
-LARGE_AT_ONCE = 2      # large plans advanced per tick
+LARGE_AT_ONCE = 1      # large plans advanced per tick (1: shortest remaining work first, one at a time)
 
 
 class Server:
@@ -165,8 +165,8 @@ class Server:
     batch, so that the many short passes of small plans run on the GPU at
     the same time as the long passes of large plans instead of waiting
     between them.  Every tick advances each live small plan, and the large
-    plans with the least remaining work (at most LARGE_AT_ONCE), by a number
-    of passes inversely proportional to its size within its class (one
+    plan(s) with the least remaining work (LARGE_AT_ONCE), by a number of
+    passes inversely proportional to its size within its class (one
     batch_advance call per class); finished plans are extracted together and
     release their memory, and requests that arrived meanwhile are admitted at
     the next tick."""
@@ -224,8 +224,8 @@ class Server:
                 mine = [l for l in live if l.cls == cls]
                 if cls == 1:
                     # large plans: the ones with the least remaining work first
-                    # (shortest remaining work keeps the mean latency low), a
-                    # few at a time so they do not slow each other down
+                    # (shortest remaining work keeps the mean latency low),
+                    # LARGE_AT_ONCE at a time so they do not slow each other down
                     mine.sort(key=lambda l: (l.total - l.done) * l.scene.n_poses)
                     mine = mine[:LARGE_AT_ONCE]
                 if not mine:
