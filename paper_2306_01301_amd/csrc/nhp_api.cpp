@@ -238,6 +238,7 @@ int plan_destroy(nhp_plan* plan) {
     for (hipGraphExec_t g : row)
       if (g) (void)hipGraphExecDestroy(g);
   if (plan->own_ws && plan->ws) (void)hipFree(plan->ws);
+  if (plan->readback) (void)hipHostFree(plan->readback);
   delete plan;
   return ok();
 }
@@ -500,9 +501,16 @@ int extract_path(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t
 // start -> goal order.
 static int finish_extract(nhp_plan* plan, nhp_step* h_steps, uint32_t cap, uint32_t* n_steps, uint32_t* best_ijt,
                           uint32_t* best_index, uint32_t* goal_value_q10, uint32_t* score_q10) {
-  uint32_t head[nhp::kExHeader];
-  HIP_CHECK(hipMemcpyAsync(head, plan->d.extract, sizeof(head), hipMemcpyDeviceToHost, plan->stream), "extract copy");
+  // the header and the first steps in one copy to pinned memory; longer
+  // plans fetch the rest with a second copy
+  const size_t first_words = nhp::kExHeader + (size_t)nhp::kReadbackSteps * nhp::kExStepWords;
+  if (!plan->readback)
+    HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&plan->readback), first_words * 4, hipHostMallocDefault),
+              "hipHostMalloc");
+  HIP_CHECK(hipMemcpyAsync(plan->readback, plan->d.extract, first_words * 4, hipMemcpyDeviceToHost, plan->stream),
+            "extract copy");
   HIP_CHECK(hipStreamSynchronize(plan->stream), "extract copy");
+  const uint32_t* head = plan->readback;
   const uint32_t status = head[0], n = head[1];
   if (n_steps) *n_steps = n;
   if (status != 0 && status != (uint32_t)(-NHP_EUNREACH))
@@ -514,12 +522,15 @@ static int finish_extract(nhp_plan* plan, nhp_step* h_steps, uint32_t cap, uint3
   if (goal_value_q10) *goal_value_q10 = head[5];
   if (score_q10) *score_q10 = head[6];
   if (n > NHP_MAX_STEPS_DEVICE || n > cap) return fail(NHP_ECAP, "plan has %u steps, buffer holds %u", n, cap);
-  std::vector<uint32_t> raw((size_t)n * nhp::kExStepWords);
-  if (n) {
-    HIP_CHECK(hipMemcpyAsync(raw.data(), plan->d.extract + nhp::kExHeader, raw.size() * 4, hipMemcpyDeviceToHost,
+  std::vector<uint32_t> rest;
+  const uint32_t* raw = head + nhp::kExHeader;
+  if (n > (uint32_t)nhp::kReadbackSteps) {
+    rest.resize((size_t)n * nhp::kExStepWords);
+    HIP_CHECK(hipMemcpyAsync(rest.data(), plan->d.extract + nhp::kExHeader, rest.size() * 4, hipMemcpyDeviceToHost,
                              plan->stream),
               "extract copy");
     HIP_CHECK(hipStreamSynchronize(plan->stream), "extract copy");
+    raw = rest.data();
   }
   for (uint32_t k = 0; k < n; k++) {  // device order is goal -> start
     const uint32_t* s = &raw[(size_t)(n - 1 - k) * nhp::kExStepWords];

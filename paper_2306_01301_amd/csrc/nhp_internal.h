@@ -129,6 +129,7 @@ hipError_t launch_init_batch(const InitJob* d_jobs, int n_jobs, size_t max_n4, h
 // extract buffer layout (uint32 words)
 constexpr int kExHeader = 16;  // status, n_steps, best i, j, T, V(best), score, best goal index, ...
 constexpr int kExStepWords = 9;
+constexpr int kReadbackSteps = 256;  // steps read back with the header in one copy
 // after the steps: a barrier counter and, per step parity and schedule
 // position, the best candidate key (2 words), its pose's value and the cost
 constexpr int kExSyncWords = 1 + 2 * 6 * 4;
@@ -241,6 +242,7 @@ struct nhp_plan {
   hipGraphExec_t cycle[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   int n_starts = 0;  // > 0: the value volume was seeded from a start set
   bool graph_failed = false;  // capture unavailable: launch the kernels directly
+  uint32_t* readback = nullptr;  // pinned: extract header and the first kReadbackSteps steps
 };
 
 namespace nhp {

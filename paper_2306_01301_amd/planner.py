@@ -285,9 +285,17 @@ class Planner:
         """`first` then `second` (-1: none), in one pass when they fuse."""
         _check(lib().sweep_pass(self._plan, int(first), int(second)), "sweep_pass")
 
+    def _step_buffer(self, cap: int):
+        """A step array of `cap` entries, kept for the next call of the same size."""
+        buf = getattr(self, "_steps_buf", None)
+        if buf is None or len(buf) != max(1, cap):
+            buf = (NhpStep * max(1, cap))()
+            self._steps_buf = buf
+        return buf
+
     def extract(self, goal: Sequence[int], radius: int = 0, w_xy: int = 1024, w_t: int = 1024,
                 cap: int = MAX_STEPS_DEVICE) -> Path:
-        steps = (NhpStep * max(1, cap))()
+        steps = self._step_buffer(cap)
         n, best, val, score = ctypes.c_uint32(), (ctypes.c_uint32 * 3)(), ctypes.c_uint32(), ctypes.c_uint32()
         gi, gj, gt = (int(v) for v in goal)
         rc = lib().extract_path(self._plan, gi, gj, gt, int(radius), int(w_xy), int(w_t), steps, int(cap),
@@ -320,7 +328,7 @@ class Planner:
         """Goal set with penalties; returns (Path, index of the chosen goal)."""
         g = np.ascontiguousarray(np.asarray(goals, np.uint32).reshape(-1))
         pen = np.ascontiguousarray(np.asarray(penalty, np.uint32))
-        steps = (NhpStep * max(1, cap))()
+        steps = self._step_buffer(cap)
         n, k, val, score = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
         rc = lib().extract_path_set(self._plan, g.ctypes.data, pen.ctypes.data, len(pen), steps, int(cap),
                                     ctypes.byref(n), ctypes.byref(k), ctypes.byref(val), ctypes.byref(score))
