@@ -33,6 +33,19 @@
 
 #include "nhp_internal.h"
 
+// Structured buffer access to the sweep kernels' volumes: the record index is
+// the pose index for both the 4-byte values and the 1-byte codes, so one
+// per-lane index addresses both (the hardware applies the record size), and
+// indices at or past the record count read 0 and drop stores instead of
+// touching memory.  (The compiler's structured-buffer operations, declared
+// by their intrinsic names.)
+__device__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset, uint32_t soffset,
+                                    int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.i32");
+__device__ uint8_t buffer_load_u8(__amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset, uint32_t soffset,
+                                  int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.i8");
+__device__ void buffer_store_u32(uint32_t v, __amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset,
+                                 uint32_t soffset, int aux) __asm("llvm.amdgcn.struct.ptr.buffer.store.i32");
+
 namespace nhp {
 namespace {
 
@@ -44,16 +57,6 @@ __device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b 
 __device__ __forceinline__ uint32_t weight(uint32_t code, uint32_t base, uint32_t lq4) {
   const uint32_t w = (base + lq4 * code) >> 8;
   return code == kHard ? kInf : w;
-}
-
-// Value volume access by 32-bit cell index.  The byte offset is formed in
-// 32 bits (volumes hold at most 2^30 poses), so the access is a uniform
-// 64-bit base plus a 32-bit per-lane offset (global_load ... saddr).
-__device__ __forceinline__ uint32_t ld_value(const uint32_t* V, uint32_t cell) {
-  return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(V) + (cell << 2));
-}
-__device__ __forceinline__ void st_value(uint32_t* V, uint32_t cell, uint32_t v) {
-  *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(V) + (cell << 2)) = v;
 }
 
 // A column in [0, 2N) reduced to [0, N): the unsigned i - N wraps above i
@@ -79,17 +82,6 @@ __device__ __forceinline__ uint32_t row_cell(uint32_t g, uint32_t x, uint32_t sh
   return g + wrap_col(x + shift, N);
 }
 
-// Structured buffer access to the row kernels' volumes: the record index is
-// the pose index for both the 4-byte values and the 1-byte codes, so one
-// per-lane index addresses both (the hardware applies the record size), and
-// indices at or past the record count read 0 and drop stores instead of
-// touching memory.
-__device__ uint32_t buffer_load_u32(__amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset, uint32_t soffset,
-                                    int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.i32");
-__device__ uint8_t buffer_load_u8(__amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset, uint32_t soffset,
-                                  int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.i8");
-__device__ void buffer_store_u32(uint32_t v, __amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset,
-                                 uint32_t soffset, int aux) __asm("llvm.amdgcn.struct.ptr.buffer.store.i32");
 constexpr int kBufferWord3 = 0x00020000;  // descriptor word 3 for untyped access on gfx9-family GPUs
 
 struct RowBuffers {
