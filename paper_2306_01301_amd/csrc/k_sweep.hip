@@ -229,6 +229,90 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, const RowBuffers
   }
 }
 
+// Sections of 64 steps (curves of up to 1024 poses in 16 waves): the 64
+// values stay in registers but the codes are packed four to a register as
+// they arrive (loaded in groups of 16, so that few byte loads hold registers
+// at once), and each use reads its weight from the LDS table.  The compiler
+// barriers every 8 steps tie the table reads to the carried value, so at
+// most 8 weights are live (holding 64 would spill).
+template <int P, bool GUARD, bool POW2>
+__device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBuffers& buf, RowShared& sh, int n_real,
+                                                  int S, int wave, int lane, bool cyclic, bool active, int xp,
+                                                  int first, int L, int N) {
+  constexpr int G = 16;  // codes per load group
+  uint32_t u[P], packed[P / 4];
+  const int xl = active ? xp : N - 1;
+#pragma unroll
+  for (int k = 0; k < P; k++) {
+    const int s = (!GUARD || first + k < L) ? first + k : L - 1;
+    u[k] = buffer_load_u32(buf.V, row_cell<POW2>(sh.row_base[s], (uint32_t)xl, POW2 ? 0u : sh.shift[s], N), 0, 0, 0);
+  }
+#pragma unroll
+  for (int h = 0; h < P / G; h++) {
+    asm volatile("" ::: "memory");
+    int xg = xl;
+    asm volatile("" : "+v"(xg));  // recompute the cells rather than keep P of them
+    uint32_t c[G];
+#pragma unroll
+    for (int e = 0; e < G; e++) {
+      const int k = h * G + e;
+      const int s = (!GUARD || first + k < L) ? first + k : L - 1;
+      c[e] = buffer_load_u8(buf.B, row_cell<POW2>(sh.row_base[s], (uint32_t)xg, POW2 ? 0u : sh.shift[s], N), 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < G / 4; q++) {
+      packed[h * (G / 4) + q] = c[4 * q] | (c[4 * q + 1] << 8) | (c[4 * q + 2] << 16) | (c[4 * q + 3] << 24);
+      asm volatile("" : "+v"(packed[h * (G / 4) + q]));
+    }
+  }
+  auto weight_of = [&](int k) { return sh.wlut[(packed[k >> 2] >> (8 * (k & 3))) & 0xffu]; };
+  {
+    uint32_t D = 0, C = kInf;
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+      if ((k & 7) == 0) asm volatile("" : "+v"(C), "+v"(D)::"memory");
+      if (!GUARD || k < n_real) {
+        const uint32_t w = weight_of(k);
+        C = sadd(umin(C, sadd(u[k], a.ct)), w);
+        D = sadd(D, w);
+      }
+    }
+    sh.aggD[wave][lane] = D;
+    sh.aggC[wave][lane] = C;
+  }
+  __syncthreads();
+  {
+    // opaque: the replay recomputes u + ct and the weights rather than the
+    // compiler keeping the compose phase's copies (which would spill)
+#pragma unroll
+    for (int q = 0; q < P / 4; q++) asm volatile("" : "+v"(packed[q]));
+#pragma unroll
+    for (int k = 0; k < P; k++) asm volatile("" : "+v"(u[k]));
+    uint32_t v = section_carry(sh.aggD, sh.aggC, S, wave, lane, cyclic);
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+      if ((k & 7) == 0) asm volatile("" : "+v"(v)::"memory");
+      const uint32_t w = weight_of(k);
+      const uint32_t uu = u[k];
+      u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+      v = sadd(umin(v, sadd(uu, a.ct)), w);
+    }
+  }
+  int xs = xp;
+  asm volatile("" : "+v"(xs));
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+      if ((k & 7) == 0) asm volatile("" ::: "memory");
+      if (!GUARD || k < n_real) {
+        buffer_store_u32(u[k], buf.V,
+                         row_cell<POW2>(sh.row_base[first + k], (uint32_t)xs, POW2 ? 0u : sh.shift[first + k], N), 0,
+                         0, 0);
+      }
+    }
+  }
+}
+
 // Row-coalesced sweep of one tile (64 curves) of a job: turns (cyclic) and
 // y-major straights.
 //   turns:     tile -> (x tile, y'); step k -> plane T_k, offsets (ox, oy)
@@ -294,12 +378,16 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
   }
   __syncthreads();  // weight table and geometry ready
 
-  uint32_t u[P];
-  uint32_t code[P];
   // Sections are P steps; steps past the curve length (when S P > L) are
   // identity maps that touch no memory.
   const int n_real = (L - wave * P) < P ? (L - wave * P) : P;  // real steps of this wave
   const int first = wave * P;
+  if constexpr (P >= 64) {
+    scan_section_wide<P, GUARD, POW2>(a, buf, sh, n_real, S, wave, lane, cyclic, active, xp, first, L, N);
+    return;
+  }
+  uint32_t u[P];
+  uint32_t code[P];
   {
     // Load this wave's section of the 64 curves.  Lanes past the grid edge
     // read a valid cell, so the loads carry no branch; lanes are independent
