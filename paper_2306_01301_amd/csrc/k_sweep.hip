@@ -229,41 +229,56 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, const RowBuffers
   }
 }
 
-// Sections of 64 steps (curves of up to 1024 poses in 16 waves): the 64
-// values stay in registers but the codes are packed four to a register as
-// they arrive (loaded in groups of 16, so that few byte loads hold registers
-// at once), and each use reads its weight from the LDS table.  The compiler
-// barriers every 8 steps tie the table reads to the carried value, so at
-// most 8 weights are live (holding 64 would spill).
+// Sections of 64 steps (curves of up to 1024 poses in 16 waves): the first
+// 32 values of a section stay in registers and the other 32 in LDS (128 KB
+// for 16 waves), the codes are packed four to a register as they arrive
+// (loaded in groups of 16, so that few byte loads hold registers at once),
+// and each use reads its weight from the LDS table.  The compiler barriers
+// every 8 steps tie the table and LDS reads to the carried value, so only a
+// few are live at once (holding all 64 values and weights would spill).
 template <int P, bool GUARD, bool POW2>
 __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBuffers& buf, RowShared& sh, int n_real,
                                                   int S, int wave, int lane, bool cyclic, bool active, int xp,
                                                   int first, int L, int N) {
-  constexpr int G = 16;  // codes per load group
-  uint32_t u[P], packed[P / 4];
+  constexpr int G = 16;      // codes per load group
+  constexpr int H = P / 2;   // values kept in registers
+  __shared__ uint32_t upper[16][P - H][64];
+  uint32_t (*hi)[64] = upper[wave];
+  uint32_t u[H], packed[P / 4];
   const int xl = active ? xp : N - 1;
+  {
+    uint32_t uh[P - H];
 #pragma unroll
-  for (int k = 0; k < P; k++) {
-    const int s = (!GUARD || first + k < L) ? first + k : L - 1;
-    u[k] = buffer_load_u32(buf.V, row_cell<POW2>(sh.row_base[s], (uint32_t)xl, POW2 ? 0u : sh.shift[s], N), 0, 0, 0);
-  }
-#pragma unroll
-  for (int h = 0; h < P / G; h++) {
-    asm volatile("" ::: "memory");
-    int xg = xl;
-    asm volatile("" : "+v"(xg));  // recompute the cells rather than keep P of them
-    uint32_t c[G];
-#pragma unroll
-    for (int e = 0; e < G; e++) {
-      const int k = h * G + e;
+    for (int k = 0; k < P; k++) {
       const int s = (!GUARD || first + k < L) ? first + k : L - 1;
-      c[e] = buffer_load_u8(buf.B, row_cell<POW2>(sh.row_base[s], (uint32_t)xg, POW2 ? 0u : sh.shift[s], N), 0, 0, 0);
+      const uint32_t v =
+          buffer_load_u32(buf.V, row_cell<POW2>(sh.row_base[s], (uint32_t)xl, POW2 ? 0u : sh.shift[s], N), 0, 0, 0);
+      if (k < H)
+        u[k] = v;
+      else
+        uh[k - H] = v;
     }
 #pragma unroll
-    for (int q = 0; q < G / 4; q++) {
-      packed[h * (G / 4) + q] = c[4 * q] | (c[4 * q + 1] << 8) | (c[4 * q + 2] << 16) | (c[4 * q + 3] << 24);
-      asm volatile("" : "+v"(packed[h * (G / 4) + q]));
+    for (int h = 0; h < P / G; h++) {
+      asm volatile("" ::: "memory");
+      int xg = xl;
+      asm volatile("" : "+v"(xg));  // recompute the cells rather than keep P of them
+      uint32_t c[G];
+#pragma unroll
+      for (int e = 0; e < G; e++) {
+        const int k = h * G + e;
+        const int s = (!GUARD || first + k < L) ? first + k : L - 1;
+        c[e] = buffer_load_u8(buf.B, row_cell<POW2>(sh.row_base[s], (uint32_t)xg, POW2 ? 0u : sh.shift[s], N), 0, 0,
+                              0);
+      }
+#pragma unroll
+      for (int q = 0; q < G / 4; q++) {
+        packed[h * (G / 4) + q] = c[4 * q] | (c[4 * q + 1] << 8) | (c[4 * q + 2] << 16) | (c[4 * q + 3] << 24);
+        asm volatile("" : "+v"(packed[h * (G / 4) + q]));
+      }
     }
+#pragma unroll
+    for (int k = 0; k < P - H; k++) hi[k][lane] = uh[k];  // a wave reads back only its own slots
   }
   auto weight_of = [&](int k) { return sh.wlut[(packed[k >> 2] >> (8 * (k & 3))) & 0xffu]; };
   {
@@ -273,7 +288,8 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
       if ((k & 7) == 0) asm volatile("" : "+v"(C), "+v"(D)::"memory");
       if (!GUARD || k < n_real) {
         const uint32_t w = weight_of(k);
-        C = sadd(umin(C, sadd(u[k], a.ct)), w);
+        const uint32_t uk = k < H ? u[k] : hi[k - H][lane];
+        C = sadd(umin(C, sadd(uk, a.ct)), w);
         D = sadd(D, w);
       }
     }
@@ -283,18 +299,22 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
   __syncthreads();
   {
     // opaque: the replay recomputes u + ct and the weights rather than the
-    // compiler keeping the compose phase's copies (which would spill)
+    // compiler keeping the compose phase's copies
 #pragma unroll
     for (int q = 0; q < P / 4; q++) asm volatile("" : "+v"(packed[q]));
 #pragma unroll
-    for (int k = 0; k < P; k++) asm volatile("" : "+v"(u[k]));
+    for (int k = 0; k < H; k++) asm volatile("" : "+v"(u[k]));
     uint32_t v = section_carry(sh.aggD, sh.aggC, S, wave, lane, cyclic);
 #pragma unroll
     for (int k = 0; k < P; k++) {
       if ((k & 7) == 0) asm volatile("" : "+v"(v)::"memory");
       const uint32_t w = weight_of(k);
-      const uint32_t uu = u[k];
-      u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+      const uint32_t uu = k < H ? u[k] : hi[k - H][lane];
+      const uint32_t out = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+      if (k < H)
+        u[k] = out;
+      else
+        hi[k - H][lane] = out;
       v = sadd(umin(v, sadd(uu, a.ct)), w);
     }
   }
@@ -305,7 +325,7 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
     for (int k = 0; k < P; k++) {
       if ((k & 7) == 0) asm volatile("" ::: "memory");
       if (!GUARD || k < n_real) {
-        buffer_store_u32(u[k], buf.V,
+        buffer_store_u32(k < H ? u[k] : hi[k - H][lane], buf.V,
                          row_cell<POW2>(sh.row_base[first + k], (uint32_t)xs, POW2 ? 0u : sh.shift[first + k], N), 0,
                          0, 0);
       }
