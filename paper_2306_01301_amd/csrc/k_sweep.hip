@@ -236,7 +236,7 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, const RowBuffers
 // and each use reads its weight from the LDS table.  The compiler barriers
 // every 8 steps tie the table and LDS reads to the carried value, so only a
 // few are live at once (holding all 64 values and weights would spill).
-template <int P, bool GUARD, bool POW2>
+template <int P, bool FUSED, bool GUARD, bool POW2>
 __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBuffers& buf, RowShared& sh, int n_real,
                                                   int S, int wave, int lane, bool cyclic, bool active, int xp,
                                                   int first, int L, int N) {
@@ -250,7 +250,7 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
     uint32_t uh[P - H];
 #pragma unroll
     for (int k = 0; k < P; k++) {
-      const int s = (!GUARD || first + k < L) ? first + k : L - 1;
+      const int s = first + k;
       const uint32_t v =
           buffer_load_u32(buf.V, row_cell<POW2>(sh.row_base[s], (uint32_t)xl, POW2 ? 0u : sh.shift[s], N), 0, 0, 0);
       if (k < H)
@@ -267,7 +267,7 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
 #pragma unroll
       for (int e = 0; e < G; e++) {
         const int k = h * G + e;
-        const int s = (!GUARD || first + k < L) ? first + k : L - 1;
+        const int s = first + k;
         c[e] = buffer_load_u8(buf.B, row_cell<POW2>(sh.row_base[s], (uint32_t)xg, POW2 ? 0u : sh.shift[s], N), 0, 0,
                               0);
       }
@@ -286,12 +286,12 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
 #pragma unroll
     for (int k = 0; k < P; k++) {
       if ((k & 7) == 0) asm volatile("" : "+v"(C), "+v"(D)::"memory");
-      if (!GUARD || k < n_real) {
-        const uint32_t w = weight_of(k);
-        const uint32_t uk = k < H ? u[k] : hi[k - H][lane];
-        C = sadd(umin(C, sadd(uk, a.ct)), w);
-        D = sadd(D, w);
-      }
+      // a step past the curve (GUARD) is the identity map: weight 0, value INF
+      const bool real = !GUARD || k < n_real;
+      const uint32_t w = real ? weight_of(k) : 0u;
+      const uint32_t uk = real ? (k < H ? u[k] : hi[k - H][lane]) : kInf;
+      C = sadd(umin(C, sadd(uk, a.ct)), w);
+      D = sadd(D, w);
     }
     sh.aggD[wave][lane] = D;
     sh.aggC[wave][lane] = C;
@@ -308,14 +308,54 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
 #pragma unroll
     for (int k = 0; k < P; k++) {
       if ((k & 7) == 0) asm volatile("" : "+v"(v)::"memory");
-      const uint32_t w = weight_of(k);
-      const uint32_t uu = k < H ? u[k] : hi[k - H][lane];
+      const bool real = !GUARD || k < n_real;
+      const uint32_t w = real ? weight_of(k) : 0u;
+      const uint32_t uu = real ? (k < H ? u[k] : hi[k - H][lane]) : kInf;
       const uint32_t out = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
       if (k < H)
         u[k] = out;
       else
         hi[k - H][lane] = out;
       v = sadd(umin(v, sadd(uu, a.ct)), w);
+    }
+  }
+  if (FUSED) {
+    // second maneuver: the steps in reverse order with its own weights
+    auto weight2_of = [&](int k) { return sh.wlut2[(packed[k >> 2] >> (8 * (k & 3))) & 0xffu]; };
+    {
+#pragma unroll
+      for (int q = 0; q < P / 4; q++) asm volatile("" : "+v"(packed[q]));
+      uint32_t D2 = 0, C2 = kInf;
+#pragma unroll
+      for (int k = P - 1; k >= 0; k--) {
+        if ((k & 7) == 7) asm volatile("" : "+v"(C2), "+v"(D2)::"memory");
+        const bool real = !GUARD || k < n_real;
+        const uint32_t w = real ? weight2_of(k) : 0u;
+        const uint32_t uk = real ? (k < H ? u[k] : hi[k - H][lane]) : kInf;
+        C2 = sadd(umin(C2, sadd(uk, a.ct2)), w);
+        D2 = sadd(D2, w);
+      }
+      sh.aggD2[wave][lane] = D2;
+      sh.aggC2[wave][lane] = C2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < P / 4; q++) asm volatile("" : "+v"(packed[q]));
+#pragma unroll
+    for (int k = 0; k < H; k++) asm volatile("" : "+v"(u[k]));
+    uint32_t v = section_carry<true>(sh.aggD2, sh.aggC2, S, wave, lane, cyclic);
+#pragma unroll
+    for (int k = P - 1; k >= 0; k--) {
+      if ((k & 7) == 7) asm volatile("" : "+v"(v)::"memory");
+      const bool real = !GUARD || k < n_real;
+      const uint32_t w = real ? weight2_of(k) : 0u;
+      const uint32_t uu = real ? (k < H ? u[k] : hi[k - H][lane]) : kInf;
+      const uint32_t out = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+      if (k < H)
+        u[k] = out;
+      else
+        hi[k - H][lane] = out;
+      v = sadd(umin(v, sadd(uu, a.ct2)), w);
     }
   }
   int xs = xp;
@@ -374,16 +414,19 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
   // Step s of a curve touches row `row` of plane T at column (x' + shift)
   // mod N: a row base shared by the 64 lanes plus a small per-lane column.
   // The geometry of all steps goes to LDS once per workgroup.
-  for (int s = threadIdx.x; s < L; s += blockDim.x) {
+  // Steps past the curve (the last section's tail when L is not a multiple
+  // of P) repeat the geometry of the last step, so loads need no clamp.
+  for (int s = threadIdx.x; s < S * P; s += blockDim.x) {
     int T, row, shift;
+    const int sc = s < L ? s : L - 1;
     if (cyclic) {
-      T = dir ? s : (L - 1 - s);
+      T = dir ? sc : (L - 1 - sc);
       shift = a.offx[T];
       row = outer + a.offy[T];
       row -= (row >= N) ? N : 0;
     } else {
       T = T0;
-      const int c = dir ? s : (L - 1 - s);
+      const int c = dir ? sc : (L - 1 - sc);
       shift = sk[c];
       shift += (shift < 0) ? N : 0;
       row = c;
@@ -403,7 +446,7 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
   const int n_real = (L - wave * P) < P ? (L - wave * P) : P;  // real steps of this wave
   const int first = wave * P;
   if constexpr (P >= 64) {
-    scan_section_wide<P, GUARD, POW2>(a, buf, sh, n_real, S, wave, lane, cyclic, active, xp, first, L, N);
+    scan_section_wide<P, FUSED, GUARD, POW2>(a, buf, sh, n_real, S, wave, lane, cyclic, active, xp, first, L, N);
     return;
   }
   uint32_t u[P];
@@ -415,9 +458,9 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
     const int xl = active ? xp : N - 1;
 #pragma unroll
     for (int k = 0; k < P; k++) {
-      // full sections need no clamp, so the geometry reads take constant
-      // offsets from one address
-      const int s = (!GUARD || first + k < L) ? first + k : L - 1;
+      // the geometry reads take constant offsets from one address (steps past
+      // the curve have a copy of the last step's geometry)
+      const int s = first + k;
       const uint32_t cell = row_cell<POW2>(sh.row_base[s], (uint32_t)xl, POW2 ? 0u : sh.shift[s], N);
       u[k] = buffer_load_u32(buf.V, cell, 0, 0, 0);
       code[k] = buffer_load_u8(buf.B, cell, 0, 0, 0);
@@ -732,10 +775,7 @@ void schedule_passes(const uint8_t* schedule, int n, uint64_t first, uint64_t co
   }
 }
 
-bool can_fuse(const DevPlan& d) {
-  const int P = pick_section(d.nt);
-  return P > 0 && P <= 32;
-}
+bool can_fuse(const DevPlan& d) { return pick_section(d.nt) > 0; }
 
 // The jobs of one pass of one plan: a row job (turns, or the y-major
 // straight planes) and, for straights, an x-major job.  Returns the number of
@@ -783,7 +823,6 @@ int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj) 
     j.lq = d.turn_lq[mu];
     j.P = pick_section(L);
     if (pass.mu2 >= 0) {
-      if (j.P > 32) return -1;  // tuning changed since can_fuse
       j.fused = 1;
       j.ct2 = d.ct[pass.mu2];
       j.lq2 = d.turn_lq[pass.mu2];
@@ -801,10 +840,7 @@ hipError_t launch_row_job_t(const SweepJob& j, hipStream_t s) {
   const int waves = (j.L + j.P - 1) / j.P;
   const dim3 grid(row_grid(j.blocks, waves, j.P)), block(64 * waves);
   switch (j.P) {
-    case 64:
-      if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
-      hipLaunchKernelGGL((row_sweep_kernel<64, false, GUARD, POW2>), grid, block, 0, s, j);
-      break;
+    case 64: hipLaunchKernelGGL((row_sweep_kernel<64, FUSED, GUARD, POW2>), grid, block, 0, s, j); break;
     case 32: hipLaunchKernelGGL((row_sweep_kernel<32, FUSED, GUARD, POW2>), grid, block, 0, s, j); break;
     case 16: hipLaunchKernelGGL((row_sweep_kernel<16, FUSED, GUARD, POW2>), grid, block, 0, s, j); break;
     case 8: hipLaunchKernelGGL((row_sweep_kernel<8, FUSED, GUARD, POW2>), grid, block, 0, s, j); break;
@@ -872,8 +908,7 @@ hipError_t launch_row_batch_t(const SweepJob* d_jobs, int n_jobs, int total_bloc
   const dim3 grid(row_grid(total_blocks, waves, P)), block(64 * waves);
   switch (P) {
     case 64:
-      if (FUSED) return hipErrorInvalidValue;  // not formed (see make_sweep_jobs)
-      hipLaunchKernelGGL((row_sweep_batch_kernel<64, false, GUARD, POW2>), grid, block, 0, s, d_jobs, n_jobs,
+      hipLaunchKernelGGL((row_sweep_batch_kernel<64, FUSED, GUARD, POW2>), grid, block, 0, s, d_jobs, n_jobs,
                          total_blocks);
       break;
     case 32:

@@ -106,8 +106,8 @@ inline bool fusable(int a, int b) {
 void schedule_passes(const uint8_t* schedule, int n, uint64_t first, uint64_t count, bool pairs,
                      std::vector<Pass>& out);
 
-// Whether a plan's turn curves fit the fused kernel (at most 32 steps per
-// wave; longer sections leave no registers for the second maneuver).
+// Whether a plan's turn curves have a section size (then consecutive turns
+// on shared circles run as one pass).
 bool can_fuse(const DevPlan& d);
 
 struct InitJob {

@@ -60,7 +60,7 @@ SCHEDULES = [
 
 @pytest.mark.parametrize("N,L,R,steps", [(64, 64, 8.0, 0), (96, 40, 5.0, 16), (136, 72, 6.0, 8),
                                          (200, 128, 9.0, 32), (96, 256, 12.0, 16),
-                                         (64, 1024, 12.0, 0)])  # 64-step sections: pairs run as single passes
+                                         (64, 1024, 12.0, 0)])  # 64-step sections, half the values in LDS
 def test_fused_cycles_match_oracle_on_random_values(N, L, R, steps):
     rng = np.random.default_rng(N * 7 + L)
     base = scenes.random_small(int(rng.integers(1 << 30)), n=N, nt=L, R=R, n_rect=max(2, N // 8))
