@@ -85,7 +85,9 @@ SWEEP_CASES = [(16, 8, 1.5, 1), (40, 24, 3.0, 1), (64, 64, 10.0, 1), (96, 48, 6.
                (200, 72, 7.5, 1), (384, 64, 10.0, 1), (256, 256, 30.0, 1),
                # the largest sides and headings: straight lines of 1024 poses and turn
                # circles of 1024 headings (64-step sections, 16 x-major tiles per row)
-               (1024, 64, 40.0, 1), (64, 1024, 12.0, 1)]
+               (1024, 64, 40.0, 1), (64, 1024, 12.0, 1),
+               # and lengths that leave the last 64-step section short
+               (1000, 16, 40.0, 1), (64, 1000, 12.0, 0)]
 
 
 @pytest.mark.parametrize("N,L,R,hc", SWEEP_CASES)
