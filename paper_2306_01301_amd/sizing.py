@@ -3,7 +3,7 @@
 * headings needed for collision checking and for unit turn steps (Sec. XIII);
 * sufficient transition cost (App. B.C, the bound before Lemma 1);
 * graph complexity and the kernel-style work count (Sec. XV, Tables 1-2);
-* pose-cell updates and algorithmic HBM bytes of a plan on this build's
+* pose-cell updates and algorithmic HBM bytes of a plan on this library's
   data layout (uint32 values, uint8 obstacle codes).
 """
 from __future__ import annotations
