@@ -84,9 +84,9 @@ __global__ __launch_bounds__(256) void reach_render_kernel(const uint32_t* __res
   __shared__ int32_t ts[kMaxTaps], tl[kMaxTaps];
   __shared__ uint32_t side[kReachMaxN * (kReachMaxN / 32)];
   const int T = blockIdx.x;
-  const int32_t* tp = taps + (size_t)T * 2 * kMaxTaps;
+  const int32_t* tp = taps + (size_t)T * (n_side + n_len);
   for (int g = threadIdx.x; g < n_side; g += blockDim.x) ts[g] = tp[g];
-  for (int g = threadIdx.x; g < n_len; g += blockDim.x) tl[g] = tp[kMaxTaps + g];
+  for (int g = threadIdx.x; g < n_len; g += blockDim.x) tl[g] = tp[n_side + g];
   __syncthreads();
   const int NW = N * W;
   for (int q = threadIdx.x; q < NW; q += blockDim.x) side[q] = or_samples(img, ts, n_side, q / W, q % W, N, W);

@@ -112,7 +112,7 @@ __device__ __forceinline__ void render_rows(const RenderJob& r, int b, int32_t* 
   const int n = SIDE ? r.n_side : r.n_len;
   // the plane's sample offsets in LDS (global loads of them would be vector
   // loads: the stores below might alias them)
-  const int32_t* tg = r.taps + (size_t)T * 2 * kMaxTaps + (SIDE ? 0 : kMaxTaps);
+  const int32_t* tg = r.taps + (size_t)T * (r.n_side + r.n_len) + (SIDE ? 0 : r.n_side);
   for (int g = threadIdx.x; g < n; g += blockDim.x) tp[g] = tg[g];
   __syncthreads();
   const uint8_t* src = SIDE ? padded_image(r) : r.side + (size_t)T * 2 * NN;

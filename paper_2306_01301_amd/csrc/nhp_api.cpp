@@ -211,7 +211,7 @@ int plan_create(const nhp_params* params, void* d_workspace, size_t workspace_by
     const void* src;
     size_t n;
   } ups[] = {
-      {d.turn_off, t.turn_off.data(), t.turn_off.size() * 4}, {d.skew, t.skew16.data(), t.skew16.size() * 2},
+      {d.turn_off, t.turn_off.data(), t.turn_off.size() * 4}, {d.skew, t.skew16->data(), t.skew16->size() * 2},
       {d.edge_len, t.edge_len.data(), t.edge_len.size() * 4}, {d.fwd, t.fwd.data(), t.fwd.size() * 4},
       {d.family, t.family.data(), t.family.size() * 4},       {d.planes, planes.data(), planes.size() * 4},
   };
@@ -273,11 +273,11 @@ int nhp::upload_taps(nhp_plan* plan, int front, int rear, int half_width) {
   if (front < 0 || rear < 0 || half_width < 0 || front > 255 || rear > 255 || half_width > 255)
     return fail(NHP_EINVAL, "box extents must be 0..255 cells");
   if (front == plan->front && rear == plan->rear && half_width == plan->half_width) return NHP_OK;
-  const int L = (int)plan->p.ntheta;
-  std::vector<int32_t> taps((size_t)L * 2 * nhp::kMaxTaps, 0);
+  const int L = (int)plan->p.ntheta, n = (2 * half_width + 1) + (front + rear + 1);
+  std::vector<int32_t> taps((size_t)L * n);
   for (int T = 0; T < L; T++)
-    nhp::render_taps_host(plan->p, plan->t, T, front, rear, half_width, &taps[(size_t)T * 2 * nhp::kMaxTaps],
-                          &taps[(size_t)T * 2 * nhp::kMaxTaps + nhp::kMaxTaps]);
+    nhp::render_taps_host(plan->p, plan->t, T, front, rear, half_width, &taps[(size_t)T * n],
+                          &taps[(size_t)T * n + 2 * half_width + 1]);
   HIP_CHECK(hipMemcpyAsync(plan->d.taps, taps.data(), taps.size() * 4, hipMemcpyHostToDevice, plan->stream),
             "sample offset upload");
   HIP_CHECK(hipStreamSynchronize(plan->stream), "sample offset upload");
@@ -597,7 +597,8 @@ int plan_get_tables(const nhp_plan* plan, int32_t* beta, int32_t* psi, int32_t* 
   if (psi) memcpy(psi, t.psi.data(), t.psi.size() * 4);
   if (family) memcpy(family, t.family.data(), t.family.size() * 4);
   if (fwd_sign) memcpy(fwd_sign, t.fwd.data(), t.fwd.size() * 4);
-  if (skew) memcpy(skew, t.skew.data(), t.skew.size() * 4);
+  if (skew)
+    for (size_t k = 0; k < t.skew16->size(); k++) skew[k] = (*t.skew16)[k];
   if (edge_len) memcpy(edge_len, t.edge_len.data(), t.edge_len.size() * 4);
   return ok();
 }

@@ -6,6 +6,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -21,11 +22,13 @@ constexpr uint32_t kMaxLq = 1u << 21;  // keeps Lq * 1276 + 128 below 2^32
 
 // Host copy of the tables of eqs. (11)-(31), built once per plan.
 struct HostTables {
-  std::vector<int32_t> beta, psi, family, fwd, skew;  // skew: [T][y']
-  std::vector<uint32_t> edge_len;                     // [mu][T], Q10, gear applied
+  std::vector<int32_t> beta, psi, family, fwd;
+  std::vector<uint32_t> edge_len;  // [mu][T], Q10, gear applied
+  // [T][y'] signed B(y', T) (|B| < nx <= 1024); depends on (nx, ntheta) only
+  // and is shared by every plan of that shape in the process
+  std::shared_ptr<const std::vector<int16_t>> skew16;
   // derived device layouts
   std::vector<int32_t> turn_off;  // [4][T]: LEFT x, LEFT y, RIGHT x, RIGHT y, reduced mod nx
-  std::vector<int16_t> skew16;    // [T][y'] signed B(y', T)
   std::vector<int32_t> planes_x;  // heading planes of the x-major straight family (I = 0)
   std::vector<int32_t> planes_y;  // heading planes of the y-major straight family (I = 1)
 };
@@ -48,7 +51,7 @@ struct DevPlan {
   int32_t* family;       // [nt]
   int32_t* planes;       // planes_x then planes_y
   int n_planes_x, n_planes_y;
-  int32_t* taps;         // [nt][2 * kMaxTaps] packed (dx & 0xffff) | (dy << 16): side then length
+  int32_t* taps;         // [nt][n_side + n_len] packed (dx & 0xffff) | (dy << 16): side then length
   uint32_t* extract;     // result header + steps
   nhp_start* starts;     // start set (NHP_MAX_STARTS entries)
   uint32_t* seeds;       // per start, seed_slots entries of kSeedWords words
@@ -191,7 +194,7 @@ struct ReachDev {
   const int16_t* skew;      // [L][N]
   const int32_t* family;    // [L]
   const int32_t* fwd;       // [L]
-  const int32_t* taps;      // [L][2][kMaxTaps]
+  const int32_t* taps;      // [L][n_side + n_len], side then length
   uint32_t* hard;           // obstacle bits, one volume
   uint32_t* levels;         // level volumes R_0 .. R_max
   uint32_t* img;            // [N][W] image bits (rendering scratch)

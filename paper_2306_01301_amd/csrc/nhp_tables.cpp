@@ -12,6 +12,9 @@
 //     x-major in all four diagonal directions).
 #include <math.h>
 
+#include <map>
+#include <mutex>
+
 #include "nhp_internal.h"
 
 namespace nhp {
@@ -31,6 +34,22 @@ int mod(long a, int n) {
   return (int)(r < 0 ? r + n : r);
 }
 
+// eq. (19): plane T is x-major (|tan| <= 1) within 45 degrees of 0 or 180
+bool x_major_plane(int L, int T) {
+  const int half = mod(T, L / 2);
+  return 8 * half <= L || 8 * half >= 3 * L;
+}
+
+// round-half-away-from-zero of |v| < 2^31, the value lround gives, without
+// the library call: the integer part is truncated and the fraction, which
+// the subtraction gives exactly, decides the rounding.
+int32_t round_half_away(double v) {
+  const double a = fabs(v);
+  const long i = (long)a;
+  const long k = i + ((a - (double)i) >= 0.5 ? 1 : 0);
+  return (int32_t)(v < 0 ? -k : k);
+}
+
 }  // namespace
 
 // sin(2 pi T / nt) from the first-quadrant table.
@@ -48,13 +67,43 @@ double grid_sin(int nt, long T) {
 
 double grid_cos(int nt, long T) { return grid_sin(nt, T + nt / 4); }
 
+namespace {
+
+// Skew table of eq. (22) for all planes of one shape: B(y', T) =
+// round(y' K_T) with K_T the plane's slope of eq. (20), in the plane's own
+// family.  A process-wide cache keyed by (nx, ntheta) builds each shape once
+// (a batch of plans mostly repeats a few shapes); past kMaxShapes entries
+// the cache starts over (plans keep their tables alive by reference).
+std::shared_ptr<const std::vector<int16_t>> skew_table(int N, int L) {
+  constexpr size_t kMaxShapes = 64;
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, std::shared_ptr<const std::vector<int16_t>>> cache;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({N, L});
+    if (it != cache.end()) return it->second;
+  }
+  auto table = std::make_shared<std::vector<int16_t>>((size_t)L * N);
+  for (int T = 0; T < L; T++) {
+    const double s = grid_sin(L, T), c = grid_cos(L, T);
+    const double K = x_major_plane(L, T) ? s / c : c / s;
+    int16_t* row = table->data() + (size_t)T * N;
+    for (int y = 0; y < N; y++) row[y] = (int16_t)round_half_away((double)y * K);
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (cache.size() >= kMaxShapes) cache.clear();
+  cache[{N, L}] = table;
+  return table;
+}
+
+}  // namespace
+
 int build_tables(const nhp_params& p, HostTables& t) {
   const int N = (int)p.nx, L = (int)p.ntheta, q = L / 4;
   t.beta.assign(L, 0);
   t.psi.assign(L, 0);
   t.family.assign(L, 0);
   t.fwd.assign(L, 0);
-  t.skew.assign((size_t)L * N, 0);
   t.edge_len.assign(6 * (size_t)L, 0);
   t.planes_x.clear();
   t.planes_y.clear();
@@ -73,13 +122,9 @@ int build_tables(const nhp_params& p, HostTables& t) {
       t.beta[T] = (int32_t)lround(alpha);
       t.psi[T] = 0;
     }
-    // eq. (19): x-major (|tan| <= 1) within 45 degrees of 0 or 180
-    const int half = mod(T, L / 2);
-    t.family[T] = (8 * half <= L || 8 * half >= 3 * L) ? 0 : 1;
+    t.family[T] = x_major_plane(L, T) ? 0 : 1;
     (t.family[T] == 0 ? t.planes_x : t.planes_y).push_back(T);
-    // eq. (20) slope, eq. (22) rounded skew, eq. (24) forward sign
-    const double K = t.family[T] == 0 ? s / c : c / s;
-    for (int y = 0; y < N; y++) t.skew[(size_t)T * N + y] = (int32_t)lround((double)y * K);
+    // eq. (24) forward sign (the skew of eqs. (20)-(22) is built per shape below)
     t.fwd[T] = t.family[T] == 0 ? (c > 0 ? 1 : -1) : (s > 0 ? 1 : -1);
     // Sec. V.D: straight edges are 1 / max(|cos|, |sin|) long
     const double straight_len = 1.0 / fmax(fabs(c), fabs(s));
@@ -101,8 +146,7 @@ int build_tables(const nhp_params& p, HostTables& t) {
     t.turn_off[2 * L + T] = mod(t.beta[(T + 2 * q) % L], N);
     t.turn_off[3 * L + T] = mod(t.beta[(T + 1 * q) % L], N);
   }
-  t.skew16.assign(t.skew.size(), 0);
-  for (size_t k = 0; k < t.skew.size(); k++) t.skew16[k] = (int16_t)t.skew[k];
+  t.skew16 = skew_table(N, L);
   return NHP_OK;
 }
 
