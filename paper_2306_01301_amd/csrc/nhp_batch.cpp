@@ -350,27 +350,28 @@ int batch_extract(nhp_batch* b, nhp_plan* const* plans, uint32_t n, const uint32
     args[k] = nhp::ExArgs{p->d, p->start[0], p->start[1], p->start[2], gi, gj, gt, (int)radius[k], w_xy_q10[k],
                           w_t_q10[k], 0, p->n_starts};
   }
+  // each plan's header and first kReadbackSteps steps come back in one copy
+  // to the pinned slot; only longer paths need a second copy
+  const size_t per_plan = nhp::kExHeader + (size_t)nhp::kReadbackSteps * nhp::kExStepWords;
   Slot* s;
-  const size_t head_words = (size_t)n * nhp::kExHeader;
-  rc = take_slot(b, std::max(args.size() * sizeof(nhp::ExArgs), head_words * 4), &s);
+  rc = take_slot(b, std::max(args.size() * sizeof(nhp::ExArgs), (size_t)n * per_plan * 4), &s);
   if (rc) return rc;
   memcpy(s->host, args.data(), args.size() * sizeof(nhp::ExArgs));
   HIP_TRY(hipMemcpyAsync(s->dev, s->host, args.size() * sizeof(nhp::ExArgs), hipMemcpyHostToDevice, b->stream),
           "job upload");
   HIP_TRY(nhp::launch_extract_batch(reinterpret_cast<const nhp::ExArgs*>(s->dev), (int)n, b->stream),
           "extract launch");
-  // the pinned staging buffer now receives the result headers (the upload
-  // ahead of them on the stream has been consumed by then)
-  uint32_t* head = reinterpret_cast<uint32_t*>(s->host);
+  // the pinned staging buffer now receives the results (the upload ahead of
+  // them on the stream has been consumed by then)
+  uint32_t* back = reinterpret_cast<uint32_t*>(s->host);
   for (uint32_t k = 0; k < n; k++)
-    HIP_TRY(hipMemcpyAsync(head + (size_t)k * nhp::kExHeader, plans[k]->d.extract, nhp::kExHeader * 4,
+    HIP_TRY(hipMemcpyAsync(back + (size_t)k * per_plan, plans[k]->d.extract, per_plan * 4,
                            hipMemcpyDeviceToHost, b->stream),
             "result copy");
   HIP_TRY(hipStreamSynchronize(b->stream), "result copy");
-  std::vector<uint32_t> heads(head, head + head_words);
   std::vector<uint32_t> raw;
   for (uint32_t k = 0; k < n; k++) {
-    const uint32_t* h = &heads[(size_t)k * nhp::kExHeader];
+    const uint32_t* h = back + (size_t)k * per_plan;
     n_steps[k] = h[1];
     if (h[0] != 0) {
       status[k] = NHP_EUNREACH;
@@ -384,16 +385,18 @@ int batch_extract(nhp_batch* b, nhp_plan* const* plans, uint32_t n, const uint32
       status[k] = NHP_ECAP;
       continue;
     }
-    raw.resize((size_t)m * nhp::kExStepWords);
-    if (m) {
+    const uint32_t* steps = h + nhp::kExHeader;
+    if (m > (uint32_t)nhp::kReadbackSteps) {
+      raw.resize((size_t)m * nhp::kExStepWords);
       HIP_TRY(hipMemcpyAsync(raw.data(), plans[k]->d.extract + nhp::kExHeader, raw.size() * 4,
                              hipMemcpyDeviceToHost, b->stream),
               "result copy");
       HIP_TRY(hipStreamSynchronize(b->stream), "result copy");
+      steps = raw.data();
     }
     nhp_step* out = h_steps + (size_t)k * cap_per_plan;
     for (uint32_t q = 0; q < m; q++) {  // device order is goal -> start
-      const uint32_t* w = &raw[(size_t)(m - 1 - q) * nhp::kExStepWords];
+      const uint32_t* w = steps + (size_t)(m - 1 - q) * nhp::kExStepWords;
       nhp_step& o = out[q];
       memset(&o, 0, sizeof(o));
       o.maneuver = (uint8_t)w[0];

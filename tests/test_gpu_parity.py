@@ -43,7 +43,7 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-TABLE_CASES = [(64, 64, 10.0, 1), (64, 64, 10.0, 0), (40, 24, 3.0, 1), (256, 256, 100.0, 1), (512, 512, 12.0, 1),
+TABLE_CASES = [(64, 64, 10.0, 1), (64, 64, 10.0, 0), (64, 64, 3.0, 1), (40, 24, 3.0, 1), (256, 256, 100.0, 1), (512, 512, 12.0, 1),
                (384, 128, 15.0, 1), (200, 72, 7.5, 0), (1024, 512, 80.0, 1)]
 
 
