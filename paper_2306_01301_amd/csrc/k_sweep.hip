@@ -177,12 +177,15 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, const RowBuffers
   {
     uint32_t v = section_carry(sh.aggD, sh.aggC, S, wave, lane, cyclic);
     // replay: a hard pose has weight INF, and w >> 31 (arithmetic) is then
-    // all ones, which forces its output to INF
+    // all ones, which forces its output to INF (weights of other codes stay
+    // below 2^24).  A fused pair forces it only in the second replay: until
+    // then a hard pose's value only ever enters a step whose weight is INF,
+    // which returns INF whatever the value, so it cannot change any result.
 #pragma unroll
     for (int k = 0; k < P; k++) {
       const uint32_t w = code[k];
       const uint32_t uu = u[k];
-      u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+      u[k] = FUSED ? umin(v, uu) : (umin(v, uu) | (uint32_t)((int32_t)w >> 31));
       v = sadd(umin(v, sadd(uu, a.ct)), w);
     }
     if (FUSED) {
@@ -311,7 +314,8 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
       const bool real = !GUARD || k < n_real;
       const uint32_t w = real ? weight_of(k) : 0u;
       const uint32_t uu = real ? (k < H ? u[k] : hi[k - H][lane]) : kInf;
-      const uint32_t out = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+      // (a fused pair forces hard poses to INF only in its second replay)
+      const uint32_t out = FUSED ? umin(v, uu) : (umin(v, uu) | (uint32_t)((int32_t)w >> 31));
       if (k < H)
         u[k] = out;
       else
