@@ -61,7 +61,9 @@ SCHEDULES = [
 @pytest.mark.parametrize("N,L,R,steps", [(64, 64, 8.0, 0), (96, 40, 5.0, 16), (136, 72, 6.0, 8),
                                          (200, 128, 9.0, 32), (96, 256, 12.0, 16),
                                          (64, 1024, 12.0, 0),   # 64-step sections, half the values in LDS
-                                         (72, 1000, 12.0, 0)])  # ... with a short last section
+                                         (72, 1000, 12.0, 0),   # ... with a short last section
+                                         (64, 512, 12.0, 64),   # 64-step sections in 8-wave workgroups
+                                         (72, 504, 12.0, 64)])  # ... with a short last section
 def test_fused_cycles_match_oracle_on_random_values(N, L, R, steps):
     rng = np.random.default_rng(N * 7 + L)
     base = scenes.random_small(int(rng.integers(1 << 30)), n=N, nt=L, R=R, n_rect=max(2, N // 8))
