@@ -269,15 +269,30 @@ int render_cspace(nhp_plan* plan, const uint8_t* d_image, int32_t front, int32_t
 
 // Uploads the footprint sample offsets of every plane for a vehicle box
 // (kept while the box does not change).
-int nhp::upload_taps(nhp_plan* plan, int front, int rear, int half_width) {
+int nhp::check_box(int front, int rear, int half_width) {
   if (front < 0 || rear < 0 || half_width < 0 || front > 255 || rear > 255 || half_width > 255)
     return fail(NHP_EINVAL, "box extents must be 0..255 cells");
-  if (front == plan->front && rear == plan->rear && half_width == plan->half_width) return NHP_OK;
+  return NHP_OK;
+}
+
+size_t nhp::taps_words(const nhp_plan* plan, int front, int rear, int half_width) {
+  return (size_t)plan->p.ntheta * (size_t)((2 * half_width + 1) + (front + rear + 1));
+}
+
+// [T][n_side + n_len]: the sideways samples of plane T, then its lengthwise ones
+void nhp::build_taps(const nhp_plan* plan, int front, int rear, int half_width, int32_t* out) {
   const int L = (int)plan->p.ntheta, n = (2 * half_width + 1) + (front + rear + 1);
-  std::vector<int32_t> taps((size_t)L * n);
   for (int T = 0; T < L; T++)
-    nhp::render_taps_host(plan->p, plan->t, T, front, rear, half_width, &taps[(size_t)T * n],
-                          &taps[(size_t)T * n + 2 * half_width + 1]);
+    nhp::render_taps_host(plan->p, plan->t, T, front, rear, half_width, out + (size_t)T * n,
+                          out + (size_t)T * n + 2 * half_width + 1);
+}
+
+int nhp::upload_taps(nhp_plan* plan, int front, int rear, int half_width) {
+  const int rc = nhp::check_box(front, rear, half_width);
+  if (rc) return rc;
+  if (front == plan->front && rear == plan->rear && half_width == plan->half_width) return NHP_OK;
+  std::vector<int32_t> taps(nhp::taps_words(plan, front, rear, half_width));
+  nhp::build_taps(plan, front, rear, half_width, taps.data());
   HIP_CHECK(hipMemcpyAsync(plan->d.taps, taps.data(), taps.size() * 4, hipMemcpyHostToDevice, plan->stream),
             "sample offset upload");
   HIP_CHECK(hipStreamSynchronize(plan->stream), "sample offset upload");

@@ -120,31 +120,56 @@ int batch_render(nhp_batch* b, nhp_plan* const* plans, const uint8_t* const* d_i
   if (n == 0) return nhp::clear_error();
   if (!d_images || !boxes_frs) return nhp::set_error(NHP_EINVAL, "images or boxes is NULL");
   std::vector<nhp::RenderJob> jobs(n);
+  // plans whose box changed get new sample offsets, built straight into the
+  // pinned staging slot after the job table and copied on the batch stream
+  std::vector<size_t> tap_at(n, 0), tap_len(n, 0);
+  size_t tap_words = 0;
   int total = 0, pad_rows = 0;
   for (uint32_t k = 0; k < n; k++) {
     nhp_plan* p = plans[k];
     if (!d_images[k]) return nhp::set_error(NHP_EINVAL, "images[%u] is NULL", k);
-    rc = nhp::upload_taps(p, boxes_frs[3 * k], boxes_frs[3 * k + 1], boxes_frs[3 * k + 2]);
+    const int f = boxes_frs[3 * k], r = boxes_frs[3 * k + 1], hw = boxes_frs[3 * k + 2];
+    rc = nhp::check_box(f, r, hw);
     if (rc) return rc;
-    nhp::RenderJob& r = jobs[k];
-    r.image = d_images[k];
-    r.side = reinterpret_cast<uint8_t*>(p->d.V);
-    r.B = p->d.B;
-    r.taps = p->d.taps;
-    r.N = p->d.nx;
-    r.nt = p->d.nt;
-    r.n_side = 2 * boxes_frs[3 * k + 2] + 1;
-    r.n_len = boxes_frs[3 * k] + boxes_frs[3 * k + 1] + 1;
-    r.blocks = nhp::render_blocks(r.N, r.nt);
-    r.first_block = total;
-    total += r.blocks;
-    r.pad_first = pad_rows;
-    pad_rows += r.N;
+    if (f != p->front || r != p->rear || hw != p->half_width) {
+      tap_at[k] = tap_words;
+      tap_len[k] = nhp::taps_words(p, f, r, hw);
+      tap_words += tap_len[k];
+    }
+    nhp::RenderJob& job = jobs[k];
+    job.image = d_images[k];
+    job.side = reinterpret_cast<uint8_t*>(p->d.V);
+    job.B = p->d.B;
+    job.taps = p->d.taps;
+    job.N = p->d.nx;
+    job.nt = p->d.nt;
+    job.n_side = 2 * hw + 1;
+    job.n_len = f + r + 1;
+    job.blocks = nhp::render_blocks(job.N, job.nt);
+    job.first_block = total;
+    total += job.blocks;
+    job.pad_first = pad_rows;
+    pad_rows += job.N;
   }
+  const size_t job_bytes = (jobs.size() * sizeof(nhp::RenderJob) + 255) & ~(size_t)255;
   Slot* s;
-  rc = take_slot(b, jobs.size() * sizeof(nhp::RenderJob), &s);
+  rc = take_slot(b, job_bytes + tap_words * 4, &s);
   if (rc) return rc;
   memcpy(s->host, jobs.data(), jobs.size() * sizeof(nhp::RenderJob));
+  int32_t* taps = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(s->host) + job_bytes);
+  for (uint32_t k = 0; k < n; k++) {
+    if (!tap_len[k]) continue;
+    nhp_plan* p = plans[k];
+    const int f = boxes_frs[3 * k], r = boxes_frs[3 * k + 1], hw = boxes_frs[3 * k + 2];
+    // work of the plan's own stream may still read its old offsets
+    if (p->stream != b->stream) HIP_TRY(hipStreamSynchronize(p->stream), "plan stream");
+    nhp::build_taps(p, f, r, hw, taps + tap_at[k]);
+    HIP_TRY(hipMemcpyAsync(p->d.taps, taps + tap_at[k], tap_len[k] * 4, hipMemcpyHostToDevice, b->stream),
+            "sample offset upload");
+    p->front = f;
+    p->rear = r;
+    p->half_width = hw;
+  }
   HIP_TRY(hipMemcpyAsync(s->dev, s->host, jobs.size() * sizeof(nhp::RenderJob), hipMemcpyHostToDevice, b->stream),
           "job upload");
   HIP_TRY(nhp::launch_render_batch(reinterpret_cast<const nhp::RenderJob*>(s->dev), (int)n, total, pad_rows,

@@ -253,4 +253,9 @@ namespace nhp {
 int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int clear_error();
 int upload_taps(nhp_plan* plan, int front, int rear, int half_width);
+// Checks a vehicle box; the sample offsets of all planes then take
+// taps_words() words, written by build_taps into `out`.
+int check_box(int front, int rear, int half_width);
+size_t taps_words(const nhp_plan* plan, int front, int rear, int half_width);
+void build_taps(const nhp_plan* plan, int front, int rear, int half_width, int32_t* out);
 }  // namespace nhp
