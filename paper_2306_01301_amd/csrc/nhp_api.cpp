@@ -373,9 +373,12 @@ static hipGraphExec_t capture_passes(nhp_plan* plan, const std::vector<nhp::Pass
 
 // n_cycles cycles of the schedule as passes (consecutive turns on shared
 // curves fused, also across cycle boundaries).  A cycle's launches come from
-// a captured graph once the call runs more than one cycle.
+// a captured graph once a plan runs more than one cycle for the second time:
+// capturing and instantiating costs more than the launches it saves on a
+// plan that is swept only once.
 static int run_cycles(nhp_plan* plan, uint32_t n_cycles) {
   const bool pairs = nhp::can_fuse(plan->d);
+  const bool graphs = n_cycles > 1 && plan->multi_cycle_runs++ > 0;
   bool skip = false;
   std::vector<nhp::Pass> passes;
   for (uint32_t n = 0; n < n_cycles; n++) {
@@ -383,8 +386,8 @@ static int run_cycles(nhp_plan* plan, uint32_t n_cycles) {
     passes.clear();
     const bool consumed = cycle_passes(plan->p, skip, pair_next, pairs, passes);
     hipGraphExec_t& g = plan->cycle[skip][pair_next];
-    if (n_cycles > 1 && !g && !plan->graph_failed) g = capture_passes(plan, passes);
-    if (g) {
+    if (graphs && !g && !plan->graph_failed) g = capture_passes(plan, passes);
+    if (graphs && g) {
       HIP_CHECK(hipGraphLaunch(g, plan->stream), "cycle graph launch");
     } else {
       for (const nhp::Pass& q : passes) HIP_CHECK(nhp::launch_sweep(plan->d, q, plan->stream), "sweep launch");

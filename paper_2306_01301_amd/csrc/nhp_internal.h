@@ -245,6 +245,7 @@ struct nhp_plan {
   hipGraphExec_t cycle[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   int n_starts = 0;  // > 0: the value volume was seeded from a start set
   bool graph_failed = false;  // capture unavailable: launch the kernels directly
+  uint32_t multi_cycle_runs = 0;  // sweeps of more than one cycle so far (graphs from the second on)
   uint32_t* readback = nullptr;  // pinned: extract header and the first kReadbackSteps steps
 };
 
