@@ -18,9 +18,12 @@ struct nhp_reach {
   nhp::ReachDev r{};
   bool has_hard = false;
   uint32_t n_levels = 0;  // level volumes holding results (0: no sweep yet)
-  // the cycles of the last multi-cycle sweep, captured as one graph
+  // the cycles of a multi-cycle sweep, captured as one graph once the same
+  // cycle count is asked for twice in a row (a count used once is launched
+  // directly: capture and instantiation cost more than the launches)
   hipGraphExec_t cycles = nullptr;
   uint32_t cycles_n = 0;
+  uint32_t last_n = 0;  // cycle count of the previous multi-cycle sweep
   bool graph_failed = false;
 };
 
@@ -201,12 +204,14 @@ int reach_sweep(nhp_reach* r, uint32_t si, uint32_t sj, uint32_t st, uint32_t n_
   HIP_TRY(hipStreamSynchronize(s), "start check");
   if ((word >> (idx % 32)) & 1u) return nhp::set_error(NHP_ESTART, "start pose (%u, %u, %u) is in collision", si, sj, st);
   HIP_TRY(nhp::launch_reach_start(r->r, (uint32_t)idx, s), "reach start launch");
-  if (n_cycles > 1 && !r->graph_failed && (!r->cycles || r->cycles_n != n_cycles)) {
+  const bool repeated = n_cycles > 1 && n_cycles == r->last_n;
+  if (n_cycles > 1) r->last_n = n_cycles;
+  if (repeated && !r->graph_failed && (!r->cycles || r->cycles_n != n_cycles)) {
     if (r->cycles) (void)hipGraphExecDestroy(r->cycles);
     r->cycles = capture_cycles(r, n_cycles);
     r->cycles_n = r->cycles ? n_cycles : 0;
   }
-  if (n_cycles > 1 && r->cycles) {
+  if (n_cycles > 1 && r->cycles && r->cycles_n == n_cycles) {
     HIP_TRY(hipGraphLaunch(r->cycles, s), "reach cycles graph launch");
   } else {
     for (uint32_t m = 0; m < n_cycles; m++)

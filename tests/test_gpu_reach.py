@@ -143,7 +143,7 @@ def test_reach_128_full_size():
         rc.sweep(start, sc.n_cycles)
         torch.cuda.synchronize()
         assert np.array_equal(_levels(rc, sc.n_cycles, B.shape), oracle.reach(prob, B, start, sc.n_cycles))
-        rc.sweep(start, 2)  # a two-cycle sweep in between (captured on its own)
+        rc.sweep(start, 2)  # a two-cycle sweep in between (launched directly: a count used once is not captured)
         torch.cuda.synchronize()
         assert np.array_equal(_levels(rc, 2, B.shape), oracle.reach(prob, B, start, 2))
     rc.close()
