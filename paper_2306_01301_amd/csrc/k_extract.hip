@@ -42,11 +42,11 @@ __device__ __forceinline__ uint32_t weight(uint32_t code, uint32_t Lq) {
   return (uint32_t)(((uint64_t)Lq * (256u + 4u * code) + 128u) >> 8);
 }
 
-// Inclusive saturating prefix sums over the block of M values per thread at
-// once (one per scheduled maneuver): thread k gets, for each m, the sum of
-// x[m] over threads 0..k.
-template <int M>
-__device__ void block_scan_sat(uint32_t (&x)[M], uint32_t (*red)[kWaves]) {
+// Inclusive saturating prefix sums over the block (NW waves) of M values per
+// thread at once (one per scheduled maneuver): thread k gets, for each m, the
+// sum of x[m] over threads 0..k.
+template <int M, int NW = kWaves>
+__device__ void block_scan_sat(uint32_t (&x)[M], uint32_t (*red)[NW]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -64,13 +64,13 @@ __device__ void block_scan_sat(uint32_t (&x)[M], uint32_t (*red)[kWaves]) {
   if (wave == 0) {
 #pragma unroll
     for (int m = 0; m < M; m++) {
-      uint32_t t = lane < kWaves ? red[m][lane] : 0u;
+      uint32_t t = lane < NW ? red[m][lane] : 0u;
 #pragma unroll
-      for (int o = 1; o < kWaves; o <<= 1) {
+      for (int o = 1; o < NW; o <<= 1) {
         const uint32_t y = __shfl_up(t, o, 64);
         if (lane >= o) t = sadd(t, y);
       }
-      if (lane < kWaves) red[m][lane] = t;
+      if (lane < NW) red[m][lane] = t;
     }
   }
   __syncthreads();
@@ -81,6 +81,7 @@ __device__ void block_scan_sat(uint32_t (&x)[M], uint32_t (*red)[kWaves]) {
   __syncthreads();
 }
 
+template <int NW = kWaves>
 __device__ uint64_t block_min_u64(uint64_t x, uint64_t* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -91,7 +92,7 @@ __device__ uint64_t block_min_u64(uint64_t x, uint64_t* red) {
   if (lane == 0) red[wave] = x;
   __syncthreads();
   uint64_t r = red[0];
-  for (int w = 1; w < kWaves; w++) r = red[w] < r ? red[w] : r;
+  for (int w = 1; w < NW; w++) r = red[w] < r ? red[w] : r;
   __syncthreads();
   return r;
 }
@@ -241,9 +242,10 @@ __device__ __forceinline__ uint32_t load_shared_word(const uint32_t* p) {
 // the workgroups exchange their best (key, value, step cost) through the
 // words after the step list; every workgroup then takes the same decision.
 // Workgroup 0 writes the result.
-template <bool GROUP>
-__device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[kWaves], uint64_t* red64,
+template <bool GROUP, int NT = kThreads>
+__device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[NT / 64], uint64_t* red64,
                                              uint32_t* flag) {
+  constexpr int NW = NT / 64;
   const DevPlan& d = x.d;
   const int N = d.nx, L = d.nt;
   const int tid = threadIdx.x;
@@ -255,7 +257,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
   if (x.n_goals > 0) {
     // ---- goal set: smallest V + penalty, ties to the earlier goal ----
     uint64_t key = ~0ull;
-    for (int k = tid; k < x.n_goals; k += kThreads) {
+    for (int k = tid; k < x.n_goals; k += NT) {
       const uint32_t* g = d.goals + 4 * (size_t)k;
       const size_t q = pose_index(N, (int)g[0], (int)g[1], (int)g[2]);
       const uint32_t v = d.V[q];
@@ -263,7 +265,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
       const uint64_t k2 = ((uint64_t)sadd(v, g[3]) << 12) | (uint64_t)k;
       key = k2 < key ? k2 : key;
     }
-    key = block_min_u64(key, red64);
+    key = block_min_u64<NW>(key, red64);
     if (key == ~0ull) {
       if (tid == 0 && writer) {
         out[0] = (uint32_t)(-NHP_EUNREACH);
@@ -287,7 +289,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
     // ---- goal search over the (2r+1)^3 window ----
     const int r = x.radius, W = 2 * r + 1, nc = W * W * W;
     uint64_t key = ~0ull;
-    for (int c = tid; c < nc; c += kThreads) {
+    for (int c = tid; c < nc; c += NT) {
       const int dx = c % W - r, dy = (c / W) % W - r, dt = c / (W * W) - r;
       const int i = modn((int)x.gi + dx, N), j = modn((int)x.gj + dy, N), T = modn((int)x.gt + dt, L);
       const size_t q = pose_index(N, i, j, T);
@@ -300,7 +302,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
                           ((uint64_t)(dt + r) << 12) | ((uint64_t)(dy + r) << 6) | (uint64_t)(dx + r);
       key = k2 < key ? k2 : key;
     }
-    key = block_min_u64(key, red64);
+    key = block_min_u64<NW>(key, red64);
     if (key == ~0ull) {
       if (tid == 0 && writer) {
         out[0] = (uint32_t)(-NHP_EUNREACH);
@@ -336,11 +338,11 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
       const uint32_t cur = (uint32_t)pose_index(N, ci, cj, cT);
       uint64_t hit = ~0ull;
       const int slots = x.n_starts * d.seed_slots;
-      for (int e = tid; e < slots; e += kThreads) {
+      for (int e = tid; e < slots; e += NT) {
         const uint32_t* sd = d.seeds + (size_t)e * kSeedWords;
         if (sd[0] == cur && sd[1] == vcur) hit = hit < (uint64_t)e ? hit : (uint64_t)e;
       }
-      hit = block_min_u64(hit, red64);
+      hit = block_min_u64<NW>(hit, red64);
       if (hit != ~0ull) {
         seed_hit = (int)hit;
         break;
@@ -377,7 +379,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
         }
       }
     }
-    block_scan_sat<M>(w, red32);  // w[m] becomes the edge sum E_k
+    block_scan_sat<M, NW>(w, red32);  // w[m] becomes the edge sum E_k
     uint64_t best = ~0ull;
 #pragma unroll
     for (int m = 0; m < M; m++) {
@@ -390,7 +392,7 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
         }
       }
     }
-    best = block_min_u64(best, red64);
+    best = block_min_u64<NW>(best, red64);
     // the thread holding the best candidate hands on its pose's value and
     // the step's cost (ct + edge sum)
     if (best != ~0ull && k == (int)(best & 2047)) {
@@ -488,12 +490,15 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
   }
 }
 
-// one workgroup per scheduled maneuver (see extract_body)
-__global__ __launch_bounds__(kThreads) void extract_kernel(ExArgs x) {
-  __shared__ uint32_t red32[6][kWaves];
-  __shared__ uint64_t red64[kWaves];
+// one workgroup per scheduled maneuver (see extract_body), NT threads: at
+// least one per candidate, i.e. more than the longest curve (max(nx, ntheta) - 1
+// poses), in as few waves as that allows
+template <int NT>
+__global__ __launch_bounds__(NT) void extract_kernel(ExArgs x) {
+  __shared__ uint32_t red32[6][NT / 64];
+  __shared__ uint64_t red64[NT / 64];
   __shared__ uint32_t flag;
-  extract_body<true>(x, red32, red64, &flag);
+  extract_body<true, NT>(x, red32, red64, &flag);
 }
 
 __global__ void clear_word_kernel(uint32_t* w) { *w = 0; }
@@ -643,7 +648,13 @@ hipError_t launch_extract(const ExArgs& x, hipStream_t s) {
                      x.d.extract + kExHeader + (size_t)NHP_MAX_STEPS_DEVICE * kExStepWords);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(extract_kernel, dim3(x.d.n_schedule), dim3(kThreads), 0, s, x);
+  const int len = x.d.nx > x.d.nt ? x.d.nx : x.d.nt;
+  if (len <= 256)
+    hipLaunchKernelGGL(extract_kernel<256>, dim3(x.d.n_schedule), dim3(256), 0, s, x);
+  else if (len <= 512)
+    hipLaunchKernelGGL(extract_kernel<512>, dim3(x.d.n_schedule), dim3(512), 0, s, x);
+  else
+    hipLaunchKernelGGL(extract_kernel<1024>, dim3(x.d.n_schedule), dim3(1024), 0, s, x);
   return hipGetLastError();
 }
 
