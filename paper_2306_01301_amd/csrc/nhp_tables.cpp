@@ -73,9 +73,10 @@ namespace {
 // round(y' K_T) with K_T the plane's slope of eq. (20), in the plane's own
 // family.  A process-wide cache keyed by (nx, ntheta) builds each shape once
 // (a batch of plans mostly repeats a few shapes); past kMaxShapes entries
-// the cache starts over (plans keep their tables alive by reference).
+// (at most 2 MB each) the cache starts over (plans keep their tables alive
+// by reference).
 std::shared_ptr<const std::vector<int16_t>> skew_table(int N, int L) {
-  constexpr size_t kMaxShapes = 64;
+  constexpr size_t kMaxShapes = 16;
   static std::mutex mu;
   static std::map<std::pair<int, int>, std::shared_ptr<const std::vector<int16_t>>> cache;
   {
