@@ -16,9 +16,10 @@
  *              separable max-dilation of the obstacle image by the vehicle
  *              box, sideways pass then lengthwise pass.
  *   init       Sec. XI step 5 preamble: V = infinity, V(start) = 0.
- *   sweep      Sec. VIII.B, Insert 1: one maneuver kernel, every curve of the
- *              maneuver walked with the node relaxation; turns walk two full
- *              loops (they are cyclic), straights one.
+ *   sweep      Sec. VIII.B: one maneuver kernel, every curve of the
+ *              maneuver walked vertex by vertex with the Star-graph
+ *              relaxation of Sec. V.A; turns walk two full loops (they are
+ *              cyclic), straights one.
  *   cycles     Sec. XVI.A: N cycles of LF, SF, RB, RF, SB, LB.
  *   goal       Sec. IX: best vertex in a window around the goal.
  *   backtrack  Sec. X, eq. (32): reverse Bellman steps back to the start.
@@ -265,15 +266,20 @@ static uint32_t edge_weight(uint32_t Lq, uint8_t kappa) {
   return w >= OR_INF ? OR_INF : (uint32_t)w;
 }
 
-/* Insert 1, one vertex: read u, store min(v, u), then move the carried value
- * along the edge leaving the vertex after optionally entering from the
- * transition state at cost ct.  A hard vertex keeps the value infinity (it
- * is removed from the graph, App. E). */
-static void relax(uint32_t* V, const uint8_t* Bv, size_t x, uint32_t ct, uint32_t Lq, uint32_t* v) {
-  uint32_t u = V[x];
-  uint32_t out = umin(*v, u);
-  V[x] = Bv[x] == OR_HARD ? OR_INF : out;
-  *v = sat_add(umin(*v, sat_add(u, ct)), edge_weight(Lq, Bv[x]));
+/* One vertex p of a maneuver's curve, relaxed in the Star graph of Sec. V.A
+ * as the sweeps of Sec. VIII.B walk it.  `arrive` is the best value reaching
+ * p along the maneuver.  Leaving the maneuver costs nothing, so the
+ * transition value of p becomes the smaller of its value before the sweep
+ * and `arrive`; the maneuver vertex at p holds the better of continuing
+ * (`arrive`) and entering the maneuver at p (the value before the sweep plus
+ * ct); the edge leaving p adds its weight for the next vertex along the
+ * curve.  Returns that next arriving value.  A hard vertex keeps the value
+ * infinity (it is removed from the graph, App. E); its edge is infinite. */
+static uint32_t relax_vertex(uint32_t* V, const uint8_t* Bv, size_t p, uint32_t ct, uint32_t Lq, uint32_t arrive) {
+  const uint32_t before = V[p];
+  const uint32_t in_maneuver = umin(arrive, sat_add(before, ct));
+  V[p] = Bv[p] == OR_HARD ? OR_INF : umin(before, arrive);
+  return sat_add(in_maneuver, edge_weight(Lq, Bv[p]));
 }
 
 /* ------------------------------------------------------------------ */
@@ -461,7 +467,7 @@ static void sweep_turn(const or_problem* p, const or_tables* tb, int mu, const u
         int32_t j = wrap((int64_t)yp + oy, N);
         for (int32_t xp = 0; xp < N; xp++) {
           int32_t i = wrap((int64_t)xp + ox, N);
-          relax(V, B, cell_index(p, i, j, T), ct, Lq, &carry[xp]);
+          carry[xp] = relax_vertex(V, B, cell_index(p, i, j, T), ct, Lq, carry[xp]);
         }
       }
     }
@@ -487,7 +493,7 @@ static void sweep_straight(const or_problem* p, const or_tables* tb, int mu, con
         for (int32_t xp = 0; xp < N; xp++) {
           int32_t i, j;
           straight_cell(p, tb, T, xp, c, &i, &j);
-          relax(V, B, cell_index(p, i, j, T), ct, Lq, &carry[xp]);
+          carry[xp] = relax_vertex(V, B, cell_index(p, i, j, T), ct, Lq, carry[xp]);
         }
       }
     }
