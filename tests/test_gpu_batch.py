@@ -141,3 +141,61 @@ def test_batch_errors():
     batch.close()
     for p in (a, b, c):
         p.close()
+
+
+def _config4_scenes():
+    """The grid shapes of the batched workload (384 and 256 sides with 256
+    and 128 headings, 128^2 x 128), with the workload's N, clutter and
+    vehicles, plus circles of 1024 headings (batched back-tracking over
+    curves longer than 512 poses)."""
+    rng = np.random.default_rng(4343)
+    shapes = [(384, 256), (384, 128), (256, 256), (128, 128)]
+    out = [scenes.random_instance(rng, sides=(n,), thetas=(t,), name="c4_%dx%d" % (n, t)) for n, t in shapes]
+    out.append(scenes.random_instance(rng, sides=(64,), thetas=(1024,), n_range=(2, 2), len_range=(4, 6),
+                                      name="tall64x1024"))
+    return out
+
+
+def _farthest_goal(sc):
+    """Oracle volumes and the free reached pose of largest value (first in
+    memory order) as the goal, so every plan back-tracks a long way."""
+    prob = problem_of(sc)
+    B = oracle.render(prob, sc.image, *sc.vehicle)
+    V = oracle.init(prob, B, sc.start)
+    oracle.cycles(prob, B, V, sc.n_cycles)
+    flat = V.reshape(-1)
+    free = (B.reshape(-1) != 255) & (flat != 0xFFFFFFFF)
+    q = int(np.flatnonzero(free & (flat == flat[free].max()))[0])
+    N = sc.nx
+    goal = (q % N, (q // N) % N, q // (N * N))
+    best, score = oracle.goal_search(prob, B, V, goal, 0, sc.w_xy, sc.w_t)
+    return B, V, goal, (best, score, oracle.backtrack(prob, B, V, sc.start, best))
+
+
+def test_batch_of_config4_shapes_matches_oracle():
+    """Plans of the batched workload's largest shapes in shared launches:
+    obstacle volume, value volume and plan of each, bit for bit."""
+    scs = _config4_scenes()
+    want = []
+    for sc in scs:
+        print("oracle %s %dx%dx%d N=%d" % (sc.name, sc.nx, sc.nx, sc.nt, sc.n_cycles), flush=True)
+        want.append(_farthest_goal(sc))
+    planners = [P.planner_for(sc) for sc in scs]
+    batch = P.Batch(len(scs))
+    batch.render(planners, [_dev(sc.image) for sc in scs], [sc.vehicle for sc in scs])
+    batch.sweep(planners, [sc.start for sc in scs], [sc.n_cycles for sc in scs])
+    paths = batch.extract(planners, [w[2] for w in want], [0] * len(scs), [sc.w_xy for sc in scs],
+                          [sc.w_t for sc in scs], cap=1024)
+    for k, sc in enumerate(scs):
+        B, V, goal, (best, score, steps) = want[k]
+        assert np.array_equal(planners[k].cspace_numpy(), B), sc.name
+        assert np.array_equal(planners[k].value_numpy(), V), sc.name
+        got = paths[k]
+        assert not isinstance(got, int), (sc.name, got)
+        assert len(steps) >= 2, sc.name
+        assert got.best == best and got.score == score, sc.name
+        assert [(s.maneuver, s.steps, s.frm, s.to, s.cost) for s in got.steps] == \
+               [(s.maneuver, s.steps, s.frm, s.to, s.cost) for s in steps], sc.name
+    batch.close()
+    for p in planners:
+        p.close()

@@ -301,3 +301,82 @@ def test_every_section_size_matches_oracle(N, L):
         P.set_section_steps(N, 0)
         P.set_section_steps(L, 0)
         P.apply_tuning()
+
+
+def _farthest_reached(B, V):
+    """The free, reached pose of largest value (first in memory order on a
+    tie): a goal whose plan walks back across most of the volume."""
+    flat = V.reshape(-1)
+    free = (B.reshape(-1) != 255) & (flat != INF)
+    vmax = flat[free].max()
+    q = int(np.flatnonzero(free & (flat == vmax))[0])
+    L, N, _ = V.shape
+    return (q % N, (q // N) % N, q // (N * N))
+
+
+def _plan_to_farthest(sc):
+    """Oracle volumes of the scene, then the farthest reached pose as goal
+    (radius 0) with its goal search and back-tracking."""
+    prob = problem_of(sc)
+    B = oracle.render(prob, sc.image, *sc.vehicle)
+    V = oracle.init(prob, B, sc.start)
+    oracle.cycles(prob, B, V, sc.n_cycles)
+    goal = _farthest_reached(B, V)
+    best, score = oracle.goal_search(prob, B, V, goal, 0, sc.w_xy, sc.w_t)
+    steps = oracle.backtrack(prob, B, V, sc.start, best)
+    return B, V, goal, (best, score), steps
+
+
+# Curves longer than 512 poses (straight lines of 1024 cells, circles of
+# 1024 headings) through the whole single-plan path, so back-tracking runs
+# its 1024-thread workgroups; and the largest grid of the batched workload.
+LONG_CASES = [
+    ("wide1024x64", lambda: scenes.random_instance(np.random.default_rng(12), sides=(1024,), thetas=(64,),
+                                                   n_range=(2, 2), name="wide1024x64")),
+    ("tall64x1024", lambda: scenes.random_instance(np.random.default_rng(13), sides=(64,), thetas=(1024,),
+                                                   n_range=(2, 2), len_range=(4, 6), name="tall64x1024")),
+    ("clutter384x256", lambda: scenes.random_instance(np.random.default_rng(10), sides=(384,), thetas=(256,),
+                                                      name="clutter384x256")),
+]
+
+
+@pytest.mark.parametrize("name,make", LONG_CASES)
+def test_long_curves_full_plan_matches_oracle(name, make):
+    sc = make()
+    note("plan %s %dx%dx%d N=%d" % (name, sc.nx, sc.nx, sc.nt, sc.n_cycles))
+    B, V, goal, want_goal, steps = _plan_to_farthest(sc)
+    assert len(steps) >= 2, "the farthest reached pose needs a multi-step plan"
+    p = _planner(sc)
+    p.render(_dev(sc.image), sc.vehicle)
+    p.sweep(sc.start, sc.n_cycles)
+    assert np.array_equal(p.cspace_numpy(), B)
+    assert np.array_equal(p.value_numpy(), V)
+    path = p.extract(goal, 0, sc.w_xy, sc.w_t)
+    _check_path(path, want_goal, steps, V)
+    p.close()
+
+
+def test_largest_serving_request_full_size():
+    """The largest request of the serving workload, 1024 x 1024 cells x 512
+    headings (a 2 GiB value volume, 1024-pose straight lines and 512-heading
+    circles), N = 4 cycles, in the launch configuration the benchmark uses:
+    obstacle volume, value volume and the plan to the farthest reached pose,
+    bit for bit against the oracle."""
+    sc = scenes.random_instance(np.random.default_rng(1306), sides=(1024,), thetas=(512,), n_range=(4, 4),
+                                occ=(0.15, 0.15), name="request1024")
+    note("request1024: GPU")
+    p = _planner(sc)
+    p.render(_dev(sc.image), sc.vehicle)
+    p.sweep(sc.start, sc.n_cycles)
+    got_B, got_V = p.cspace_numpy(), p.value_numpy()
+    note("request1024: oracle")
+    t = time.time()
+    B, V, goal, want_goal, steps = _plan_to_farthest(sc)
+    note("request1024: oracle %.1f s, plan of %d steps" % (time.time() - t, len(steps)))
+    assert np.array_equal(got_B, B)
+    del got_B, B
+    assert np.array_equal(got_V, V)
+    del got_V
+    path = p.extract(goal, 0, sc.w_xy, sc.w_t)
+    p.close()
+    _check_path(path, want_goal, steps, V)

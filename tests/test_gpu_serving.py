@@ -45,3 +45,52 @@ def test_alone_in_a_batch_and_served_agree():
     assert any(q.arrival < r.arrival and r.admitted < q.finished for q in served for r in served)
     summary = serving.latency_summary(served)
     assert summary["n"] == len(reqs) and summary["p99_ms"] >= summary["p50_ms"] > 0
+
+
+def _oracle_key(sc):
+    """What the oracle gives a request: status, value-volume digest, goal and
+    plan (the same key as _key)."""
+    import hashlib
+
+    import oracle
+    from tests.common import problem_of
+
+    prob = problem_of(sc)
+    B = oracle.render(prob, sc.image, *sc.vehicle)
+    V = oracle.init(prob, B, sc.start)
+    oracle.cycles(prob, B, V, sc.n_cycles)
+    digest = hashlib.sha1(V.tobytes()).hexdigest()
+    try:
+        best, score = oracle.goal_search(prob, B, V, sc.goal, sc.goal_radius, sc.w_xy, sc.w_t)
+        steps = oracle.backtrack(prob, B, V, sc.start, best)
+    except oracle.OracleError as e:
+        return (e.rc, digest, None, None)
+    value = int(V[best[2], best[1], best[0]])
+    return (0, digest, (best, value, score), [(s.maneuver, s.steps, s.frm, s.to, s.cost) for s in steps])
+
+
+def test_served_results_match_oracle(monkeypatch):
+    """Small and large requests at once (the large class lowered to 2^22
+    poses so both classes and both streams run together, with a 512-side
+    request among the large), admitted under a budget that makes requests
+    wait: every served result equals the oracle's."""
+    import os
+
+    import oracle
+
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    monkeypatch.setattr(serving, "LARGE_POSES", 1 << 22)
+    rng = np.random.default_rng(78)
+    reqs = [scenes.random_instance(rng, sides=(64, 128), thetas=(64, 128), n_range=(2, 5), name="s%02d" % k)
+            for k in range(6)]
+    reqs.insert(1, scenes.random_instance(rng, sides=(512,), thetas=(128,), n_range=(3, 3), name="L512"))
+    reqs.insert(4, scenes.random_instance(rng, sides=(256,), thetas=(256,), n_range=(3, 3), name="L256"))
+    assert sum(sc.n_poses >= serving.LARGE_POSES for sc in reqs) == 2
+    arrivals = scenes.poisson_arrivals(6, 200.0, len(reqs))
+    budget = serving.footprint_bytes(reqs[1]) + 2 * max(serving.footprint_bytes(sc) for sc in reqs[2:])
+    srv = serving.Server(budget, max_live=8, digests=True)
+    served = srv.run(reqs, arrivals)
+    srv.close()
+    for sc, r in zip(reqs, served):
+        print("request %s %dx%dx%d N=%d: oracle" % (sc.name, sc.nx, sc.nx, sc.nt, sc.n_cycles), flush=True)
+        assert _key(r) == _oracle_key(sc), sc.name
