@@ -218,6 +218,25 @@ int extract_path(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t
                  uint32_t* n_steps, uint32_t* best_ijt, uint32_t* goal_value_q10,
                  uint32_t* score_q10);
 
+/* For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation): extract_path with the same
+ * arguments, results and errors, but this call allocates nothing, neither
+ * device nor pinned host memory.  Its extract area (result header, the step
+ * list of up to NHP_MAX_STEPS_DEVICE steps, the back-tracking kernel's
+ * barrier counter and exchange words: NHP_NOALLOC_EXTRACT_BYTES bytes) is a
+ * fixed device array of the library, one per GPU, held until the process
+ * ends; its size does not depend on the grid, so every plan fits (a walk
+ * longer than NHP_MAX_STEPS_DEVICE steps is NHP_EUNREACH, as in
+ * extract_path).  The steps are copied straight into h_steps.  All calls on
+ * one GPU share that GPU's area: calls that overlap on one GPU (two threads,
+ * or two streams) race and must be serialised by the caller.  Synchronises
+ * the plan's stream. */
+#define NHP_NOALLOC_EXTRACT_BYTES ((16u + NHP_MAX_STEPS_DEVICE * 9u + 49u) * 4u)
+int extract_path_noalloc(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t radius,
+                         uint32_t w_xy_q10, uint32_t w_t_q10, nhp_step* h_steps, uint32_t cap,
+                         uint32_t* n_steps, uint32_t* best_ijt, uint32_t* goal_value_q10,
+                         uint32_t* score_q10);
+
 /* Device pointers of the plan's value and obstacle volumes (for parity
  * checks and checkpoints; owned by the plan).  Either output may be NULL. */
 /* Goal set with penalties (Sec. IX: the criterion is the reward of the

@@ -11,6 +11,8 @@
 // V(p_k) + ct_mu + E_k, and a block-wide minimum of the packed key
 // (candidate, schedule position, k) picks the next pose.  Curves are at most
 // 1024 poses long, so one thread per candidate suffices.
+#include <mutex>
+
 #include "nhp_internal.h"
 
 namespace nhp {
@@ -661,6 +663,43 @@ hipError_t launch_extract(const ExArgs& x, hipStream_t s) {
 hipError_t launch_seed(const DevPlan& d, int n_starts, hipStream_t s) {
   hipLaunchKernelGGL(seed_kernel, dim3(n_starts), dim3(kThreads), 0, s, d);
   return hipGetLastError();
+}
+
+// ---- extract area of extract_path_noalloc ----
+// One extract area (header, step list, barrier counter and exchange area) per
+// device, in a file-scope device array instead of a plan's workspace, for
+// callers that cannot allocate.  Every call on a device shares its copy.
+static __device__ __align__(256) uint32_t scratch[kNoAllocExtractWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+}  // namespace
+
+hipError_t noalloc_extract_area(int device, uint32_t** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    // the array's name is a host-side stand-in: its device address comes
+    // from the runtime, once per device, with that device current
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = static_cast<uint32_t*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_extract_batch(const ExArgs* d_args, int n, hipStream_t s) {

@@ -515,6 +515,75 @@ int extract_path(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t
   return finish_extract(plan, h_steps, cap, n_steps, best_ijt, nullptr, goal_value_q10, score_q10);
 }
 
+// extract_path with its extract area in the library's file-scope device
+// array: no allocation of any kind on this path (the header comes back into a
+// local array, the steps straight into the caller's step buffer, which is
+// then put into start -> goal order in place).
+static_assert(sizeof(nhp_step) == nhp::kExStepWords * 4, "a device step record and an nhp_step have one size");
+
+int extract_path_noalloc(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, uint32_t radius, uint32_t w_xy_q10,
+                         uint32_t w_t_q10, nhp_step* h_steps, uint32_t cap, uint32_t* n_steps, uint32_t* best_ijt,
+                         uint32_t* goal_value_q10, uint32_t* score_q10) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!plan->has_value) return fail(NHP_ESTATE, "extract_path_noalloc before sweep_n_turns");
+  if (gi >= plan->p.nx || gj >= plan->p.nx || gt >= plan->p.ntheta) return fail(NHP_EINVAL, "goal outside the grid");
+  if (radius > (uint32_t)nhp::kMaxRadius) return fail(NHP_EINVAL, "goal radius must be 0..%d", nhp::kMaxRadius);
+  if (cap > 0 && !h_steps) return fail(NHP_EINVAL, "h_steps is NULL");
+  uint32_t* area = nullptr;
+  HIP_CHECK(nhp::noalloc_extract_area(plan->device, &area), "extract area lookup");
+  nhp::ExArgs x{};
+  x.d = plan->d;
+  x.d.extract = area;  // the kernels take the looked-up address, never the array's name
+  x.si = plan->start[0];
+  x.sj = plan->start[1];
+  x.st = plan->start[2];
+  x.gi = gi;
+  x.gj = gj;
+  x.gt = gt;
+  x.radius = (int)radius;
+  x.w_xy = w_xy_q10;
+  x.w_t = w_t_q10;
+  x.n_starts = plan->n_starts;
+  HIP_CHECK(nhp::launch_extract(x, plan->stream), "extract launch");
+  uint32_t head[nhp::kExHeader];
+  HIP_CHECK(hipMemcpyAsync(head, area, sizeof(head), hipMemcpyDeviceToHost, plan->stream), "extract copy");
+  HIP_CHECK(hipStreamSynchronize(plan->stream), "extract copy");
+  const uint32_t status = head[0], n = head[1];
+  if (n_steps) *n_steps = n;
+  if (status != 0 && status != (uint32_t)(-NHP_EUNREACH))
+    return fail(NHP_EHIP, "extract kernel returned status %u", status);
+  if (status == (uint32_t)(-NHP_EUNREACH))
+    return fail(NHP_EUNREACH, "no reached pose in the goal window (or back-tracking lost the path)");
+  if (best_ijt) memcpy(best_ijt, head + 2, 3 * sizeof(uint32_t));
+  if (goal_value_q10) *goal_value_q10 = head[5];
+  if (score_q10) *score_q10 = head[6];
+  if (n > NHP_MAX_STEPS_DEVICE || n > cap) return fail(NHP_ECAP, "plan has %u steps, buffer holds %u", n, cap);
+  if (n == 0) return ok();
+  HIP_CHECK(hipMemcpyAsync(h_steps, area + nhp::kExHeader, (size_t)n * sizeof(nhp_step), hipMemcpyDeviceToHost,
+                           plan->stream),
+            "extract copy");
+  HIP_CHECK(hipStreamSynchronize(plan->stream), "extract copy");
+  // device records are goal -> start: reverse them and convert each
+  auto convert = [](const uint32_t* s, nhp_step& o) {
+    memset(&o, 0, sizeof(o));
+    o.maneuver = (uint8_t)s[0];
+    o.steps = s[1];
+    memcpy(o.from_ijt, s + 2, 3 * sizeof(uint32_t));
+    memcpy(o.to_ijt, s + 5, 3 * sizeof(uint32_t));
+    o.cost_q10 = s[8];
+  };
+  for (uint32_t a = 0, b = n - 1; a <= b; a++, b--) {
+    uint32_t ra[nhp::kExStepWords], rb[nhp::kExStepWords];
+    memcpy(ra, &h_steps[a], sizeof(ra));
+    memcpy(rb, &h_steps[b], sizeof(rb));
+    convert(rb, h_steps[a]);
+    if (a != b) convert(ra, h_steps[b]);
+    if (b == 0) break;
+  }
+  return ok();
+}
+
 // Reads back the result of an extract launch: header, then the steps in
 // start -> goal order.
 static int finish_extract(nhp_plan* plan, nhp_step* h_steps, uint32_t cap, uint32_t* n_steps, uint32_t* best_ijt,

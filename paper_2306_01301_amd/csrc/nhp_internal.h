@@ -159,6 +159,12 @@ struct ExArgs {
   int n_starts;  // > 0: the plan ends at a seed of the start set in d.seeds
 };
 hipError_t launch_extract_batch(const ExArgs* d_args, int n, hipStream_t s);
+// Words of one extract area (header, steps, barrier counter, exchange area).
+constexpr size_t kNoAllocExtractWords = kExHeader + (size_t)NHP_MAX_STEPS_DEVICE * kExStepWords + kExSyncWords;
+static_assert(kNoAllocExtractWords * 4 == NHP_NOALLOC_EXTRACT_BYTES, "the header states the area's size");
+// Device address of the file-scope extract area on `device` (looked up on
+// the first call per device; no allocation).
+hipError_t noalloc_extract_area(int device, uint32_t** out);
 
 // Rendering of one plan: sideways pass from the image into `side`, then the
 // lengthwise pass into B.  Batched launches list several plans.

@@ -76,6 +76,8 @@ SIGNATURES = {
     "schedule_passes": (ctypes.c_int, [_vp, _u32, ctypes.c_uint64, ctypes.c_uint64, _i32, _vp, _vp, _u32, _PU32]),
     "extract_path": (ctypes.c_int, [_vp, _u32, _u32, _u32, _u32, _u32, _u32, ctypes.POINTER(NhpStep), _u32,
                                     _PU32, _PU32, _PU32, _PU32]),
+    "extract_path_noalloc": (ctypes.c_int, [_vp, _u32, _u32, _u32, _u32, _u32, _u32, ctypes.POINTER(NhpStep),
+                                            _u32, _PU32, _PU32, _PU32, _PU32]),
     "plan_device_ptrs": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "plan_get_tables": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "plan_last_error": (ctypes.c_char_p, []),
@@ -301,6 +303,22 @@ class Planner:
         rc = lib().extract_path(self._plan, gi, gj, gt, int(radius), int(w_xy), int(w_t), steps, int(cap),
                                 ctypes.byref(n), best, ctypes.byref(val), ctypes.byref(score))
         _check(rc, "extract_path")
+        out = [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_ijt),
+                    tuple(int(v) for v in s.to_ijt), int(s.cost_q10)) for s in steps[: n.value]]
+        return Path(out, tuple(int(v) for v in best), int(val.value), int(score.value))
+
+    def extract_noalloc(self, goal: Sequence[int], radius: int = 0, w_xy: int = 1024, w_t: int = 1024,
+                        steps=None) -> Path:
+        """extract_path_noalloc: as extract, with the library's fixed extract
+        area.  `steps`: a caller-made NhpStep array (default: the planner's
+        cached one of MAX_STEPS_DEVICE entries)."""
+        if steps is None:
+            steps = self._step_buffer(MAX_STEPS_DEVICE)
+        n, best, val, score = ctypes.c_uint32(), (ctypes.c_uint32 * 3)(), ctypes.c_uint32(), ctypes.c_uint32()
+        gi, gj, gt = (int(v) for v in goal)
+        rc = lib().extract_path_noalloc(self._plan, gi, gj, gt, int(radius), int(w_xy), int(w_t), steps, len(steps),
+                                        ctypes.byref(n), best, ctypes.byref(val), ctypes.byref(score))
+        _check(rc, "extract_path_noalloc")
         out = [Step(int(s.maneuver), int(s.steps), tuple(int(v) for v in s.from_ijt),
                     tuple(int(v) for v in s.to_ijt), int(s.cost_q10)) for s in steps[: n.value]]
         return Path(out, tuple(int(v) for v in best), int(val.value), int(score.value))
