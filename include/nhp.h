@@ -187,6 +187,15 @@ int sweep_one(nhp_plan* plan, uint32_t maneuver);
  * either way.  Errors: NHP_ESTATE, NHP_EINVAL. */
 int sweep_pass(nhp_plan* plan, int32_t first, int32_t second);
 
+/* The straight maneuver `maneuver` (NHP_SF or NHP_SB; Insert 1 over the
+ * lines of eqs. 29-31) on the heading planes of one family of eq. (19)
+ * only: family 1 = the planes whose lines advance one row per step (|tan
+ * theta| > 1), family 0 = one column per step.  The families hold disjoint
+ * planes, so both, in either order, equal sweep_one(maneuver); each family
+ * is a single kernel launch, so events around the calls time each kernel.
+ * Errors: NHP_ESTATE, NHP_EINVAL. */
+int sweep_straight_family(nhp_plan* plan, uint32_t maneuver, uint32_t family);
+
 /* Host only (no device work): the passes that sweeps n_steps sweeps of a
  * schedule starting at sweep number first_step (sweep k applies
  * schedule[k % n_schedule]) are grouped into, as sweep_n_turns and
@@ -237,8 +246,6 @@ int extract_path_noalloc(nhp_plan* plan, uint32_t gi, uint32_t gj, uint32_t gt, 
                          uint32_t* n_steps, uint32_t* best_ijt, uint32_t* goal_value_q10,
                          uint32_t* score_q10);
 
-/* Device pointers of the plan's value and obstacle volumes (for parity
- * checks and checkpoints; owned by the plan).  Either output may be NULL. */
 /* Goal set with penalties (Sec. IX: the criterion is the reward of the
  * final vertex minus the cost to get there; a reward is passed as its
  * shortfall from the largest reward, so penalty_q10 >= 0): the goal k
@@ -251,6 +258,8 @@ int extract_path_set(nhp_plan* plan, const uint32_t* goals_ijt, const uint32_t* 
                      nhp_step* h_steps, uint32_t cap, uint32_t* n_steps, uint32_t* best_index,
                      uint32_t* goal_value_q10, uint32_t* score_q10);
 
+/* Device pointers of the plan's value and obstacle volumes (for parity
+ * checks and checkpoints; owned by the plan).  Either output may be NULL. */
 int plan_device_ptrs(const nhp_plan* plan, uint32_t** d_value, uint8_t** d_cspace);
 
 /* Copies the host tables out (each host array may be NULL):

@@ -887,19 +887,21 @@ hipError_t launch_force_walls(const DevPlan& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s) {
+hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s) { return launch_sweep_part(d, pass, 3, s); }
+
+hipError_t launch_sweep_part(const DevPlan& d, Pass pass, int parts, hipStream_t s) {
   SweepJob row{}, xmaj{};
   if (make_sweep_jobs(d, pass, &row, &xmaj) < 0) {
     // a pair that cannot share a pass: one pass each
     const hipError_t e = launch_sweep(d, Pass{pass.mu, (int8_t)-1}, s);
     return e != hipSuccess ? e : launch_sweep(d, Pass{pass.mu2, (int8_t)-1}, s);
   }
-  if (row.blocks) {
+  if (row.blocks && (parts & 1)) {
     if (!row.P) return hipErrorInvalidValue;
     const hipError_t e = launch_row_job(row, s);
     if (e != hipSuccess) return e;
   }
-  if (xmaj.blocks) {
+  if (xmaj.blocks && (parts & 2)) {
     hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT>), dim3(xmajor_grid(xmaj.blocks)), dim3(XNT), 0, s, xmaj);
     return hipGetLastError();
   }

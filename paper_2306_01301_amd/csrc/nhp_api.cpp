@@ -464,6 +464,17 @@ int sweep_pass(nhp_plan* plan, int32_t first, int32_t second) {
   return ok();
 }
 
+int sweep_straight_family(nhp_plan* plan, uint32_t maneuver, uint32_t family) {
+  int rc = check_plan(plan);
+  if (rc) return rc;
+  if (!plan->has_cspace) return fail(NHP_ESTATE, "sweep_straight_family before render_cspace/plan_set_cspace");
+  if (maneuver != NHP_SF && maneuver != NHP_SB) return fail(NHP_EINVAL, "maneuver must be NHP_SF or NHP_SB");
+  if (family > 1) return fail(NHP_EINVAL, "family must be 0 or 1");
+  HIP_CHECK(nhp::launch_sweep_part(plan->d, nhp::Pass{(int8_t)maneuver, (int8_t)-1}, family ? 1 : 2, plan->stream),
+            "sweep launch");
+  return ok();
+}
+
 int schedule_passes(const uint8_t* schedule, uint32_t n_schedule, uint64_t first_step, uint64_t n_steps,
                     int32_t pairs, int8_t* first, int8_t* second, uint32_t cap, uint32_t* n_passes) {
   if (!schedule || n_schedule < 1 || n_schedule > 6 || !n_passes) return fail(NHP_EINVAL, "bad schedule or NULL count");

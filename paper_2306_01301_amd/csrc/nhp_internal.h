@@ -146,6 +146,9 @@ hipError_t launch_seed(const DevPlan& d, int n_starts, hipStream_t s);
 hipError_t launch_init(const DevPlan& d, uint32_t start_index, hipStream_t s);
 hipError_t launch_force_walls(const DevPlan& d, hipStream_t s);
 hipError_t launch_sweep(const DevPlan& d, Pass pass, hipStream_t s);
+// Part of a pass: parts bit 0 = the row kernel (turn curves, or the y-major
+// straight planes), bit 1 = the x-major straight planes.
+hipError_t launch_sweep_part(const DevPlan& d, Pass pass, int parts, hipStream_t s);
 hipError_t launch_render(const DevPlan& d, const uint8_t* image, int n_side, int n_len, hipStream_t s);
 hipError_t launch_extract(const struct ExArgs& x, hipStream_t s);
 

@@ -69,6 +69,7 @@ SIGNATURES = {
     "sweep_resume": (ctypes.c_int, [_vp, _u32]),
     "sweep_one": (ctypes.c_int, [_vp, _u32]),
     "sweep_pass": (ctypes.c_int, [_vp, _i32, _i32]),
+    "sweep_straight_family": (ctypes.c_int, [_vp, _u32, _u32]),
     "sweep_from_set": (ctypes.c_int, [_vp, _vp, _u32, _u32]),
     "soft_cost_image": (ctypes.c_int, [_vp, _vp, _vp, _vp, _u32]),
     "extract_path_set": (ctypes.c_int, [_vp, _vp, _vp, _u32, ctypes.POINTER(NhpStep), _u32, _PU32, _PU32, _PU32,
@@ -286,6 +287,10 @@ class Planner:
     def sweep_pass(self, first: int, second: int = -1) -> None:
         """`first` then `second` (-1: none), in one pass when they fuse."""
         _check(lib().sweep_pass(self._plan, int(first), int(second)), "sweep_pass")
+
+    def sweep_straight_family(self, maneuver: int, family: int) -> None:
+        """Straight `maneuver` on the planes of one family (1: a row per step, 0: a column per step)."""
+        _check(lib().sweep_straight_family(self._plan, int(maneuver), int(family)), "sweep_straight_family")
 
     def _step_buffer(self, cap: int):
         """A step array of `cap` entries, kept for the next call of the same size."""

@@ -117,6 +117,34 @@ def test_each_sweep_matches_oracle_on_random_values(N, L, R, hc):
     p.close()
 
 
+@pytest.mark.parametrize("N,L,R", [(64, 64, 10.0), (200, 72, 7.5), (512, 40, 20.0)])
+def test_straight_families_separately_match_oracle(N, L, R):
+    """sweep_straight_family over both families, in either order, equals
+    the oracle's straight sweep (the families hold disjoint planes)."""
+    rng = np.random.default_rng(N * 7 + L)
+    sc = scenes.random_small(int(rng.integers(1 << 30)), n=N, nt=L, R=R, n_rect=max(2, N // 8)).with_(
+        vehicle=(3, 1, 1))
+    prob = problem_of(sc)
+    B = oracle.render(prob, sc.image, *sc.vehicle)
+    p = _planner(sc)
+    p.set_cspace(_dev(B))
+    for mu in (oracle.SF, oracle.SB):
+        for order in ((0, 1), (1, 0)):
+            note("straight families %s mu=%s order=%s" % ((N, L, R), oracle.NAMES[mu], order))
+            V = rng.integers(0, 1 << 24, size=B.shape, dtype=np.uint64).astype(np.uint32)
+            V[rng.random(B.shape) < 0.3] = INF
+            p.value.copy_(_dev(V.view(np.int32)))
+            for fam in order:
+                p.sweep_straight_family(mu, fam)
+            want = V.copy()
+            oracle.sweep(prob, mu, B, want)
+            assert np.array_equal(p.value_numpy(), want)
+    with pytest.raises(P.NhpError) as e:
+        p.sweep_straight_family(oracle.LF, 0)
+    assert e.value.rc == P.EINVAL
+    p.close()
+
+
 PLAN_CASES = [
     ("plain_64", lambda: scenes.plain_64(), None),
     ("plain_64_s7", lambda: scenes.plain_64(7), None),
