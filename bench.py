@@ -35,20 +35,20 @@ METRIC = "pose-cell updates/s and plans/s at 512³ N=20; p50/p99 plan latency ba
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 9  # read V (4 B) + read obstacle code (1 B) + write V (4 B), per pose and pass
 TURNS = (0, 2, 3, 5)   # LF, RB, RF, LB
-# pass kinds: the kernels one pass of each kind launches
-PASS_KINDS = {
-    "fused_turn": "row_sweep_kernel<32, true, false, true> (two turn maneuvers on shared circles in one pass)",
-    "turn": "row_sweep_kernel<32, false, false, true> (one turn maneuver)",
-    "straight": "row_sweep_kernel<32, false, false, true> (y-major planes) + xmajor_sweep_kernel<32, 256> (x-major planes)",
+# the sweep kernels of the maze workload (512-pose curves: 32-step sections)
+KERNELS = {
+    "fused_turn": "row_sweep_kernel<32, true, false, true, true> (two turn maneuvers on shared circles in one launch)",
+    "turn": "row_sweep_kernel<32, false, false, true, true> (one turn maneuver)",
+    "straight_y": "row_sweep_kernel<32, false, false, true, false> (straight maneuver, y-major planes)",
+    "straight_x": "xmajor_sweep_kernel (straight maneuver, x-major planes)",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweeps_maze_512.json")
 
 
-def pass_kind(first: int, second: int) -> str:
+def kernel_kind(first: int, second: int) -> str:
     if second >= 0:
         return "fused_turn"
     return "turn" if first in TURNS else "straight"
-
 
 
 def kernel_source_hash() -> str:
@@ -59,49 +59,90 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kind: str):
-    """HBM bytes per pass of this kind from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+def measured_traffic():
+    """HBM bytes per launch of each sweep kernel from the committed rocprofv3
+    counter summary, or {} when the kernel source changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     if t.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    return t.get("bytes_per_pass", {}).get(kind)
+        return {}
+    return t.get("bytes_per_launch", {})
 
 
-def cpu_model() -> str:
+def host_cpu() -> dict:
+    """The host's processor as lscpu and /proc/cpuinfo name it, and the CPUs
+    this process may run on."""
+    info = {"nproc": None, "os_cpu_count": os.cpu_count(), "affinity": None, "lscpu_model": None,
+            "cpuinfo_model": None, "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        info["nproc"] = int(subprocess.check_output(["nproc"], text=True).strip())
+    except Exception:
+        pass
     try:
         out = subprocess.check_output(["lscpu"], text=True)
         for line in out.splitlines():
-            if line.startswith("Model name"):
-                return line.split(":", 1)[1].strip()
+            key, _, val = line.partition(":")
+            if key.strip() in ("Model name", "Vendor ID", "CPU family", "Model", "Thread(s) per core",
+                               "Core(s) per socket", "Socket(s)", "CPU(s)"):
+                info.setdefault("lscpu", {})[key.strip()] = val.strip()
+                if key.strip() == "Model name":
+                    info["lscpu_model"] = val.strip()
     except Exception:
         pass
-    return platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpuinfo_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return info
 
 
-def cpu_baseline(scene, cycles: int):
-    """The oracle as it stands, on the host's cores, on `cycles` maneuver
-    cycles of the same workload (a bounded sample of the 20)."""
+def cpu_baseline(scene, cycles_all: int, cycles_one: int):
+    """The oracle as it stands, built -O3 -march=native -fopenmp on the host
+    it runs on: all 20 cycles on all the host CPUs this process may use, and
+    a bounded sample of the cycles on one core."""
     import oracle
 
-    oracle.build()
-    threads = oracle.set_threads(os.cpu_count() or 1)
+    lib = oracle.build(native=True)
     prob = oracle.Problem(scene.nx, scene.nt, scene.R, scene.half_cell, list(scene.schedule), list(scene.ct),
                           list(scene.gear))
+    host = host_cpu()
+    want = host["affinity"] or os.cpu_count() or 1
+    if host["omp_num_threads"]:
+        want = min(want, int(host["omp_num_threads"]))
     B = oracle.render(prob, scene.image, *scene.vehicle)
-    V = oracle.init(prob, B, scene.start)
-    t0 = time.perf_counter()
-    oracle.cycles(prob, B, V, cycles)
-    dt = time.perf_counter() - t0
-    updates = len(scene.schedule) * cycles * scene.n_poses
-    return {"value": updates / dt, "unit": "pose-cell updates/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d maneuver cycles (%d sweeps, %.2e pose updates) of %s on %d threads of %s, %.1f s"
-                      % (cycles, scene.n_cycles, len(scene.schedule) * cycles, updates, scene.name, threads,
-                         cpu_model(), dt)}
+    V0 = oracle.init(prob, B, scene.start)
+    runs = {}
+    for name, threads, cycles in (("all", want, cycles_all), ("one", 1, cycles_one)):
+        if cycles <= 0:
+            continue
+        used = oracle.set_threads(threads)
+        V = V0.copy()
+        t0 = time.perf_counter()
+        oracle.cycles(prob, B, V, cycles)
+        dt = time.perf_counter() - t0
+        updates = len(scene.schedule) * cycles * scene.n_poses
+        runs[name] = {"value": updates / dt, "unit": "pose-cell updates/s", "cores": used, "seconds": dt,
+                      "sample": "%d of %d maneuver cycles (%d sweeps, %.2e pose updates) of %s on %d thread%s"
+                                % (cycles, scene.n_cycles, len(scene.schedule) * cycles, updates, scene.name, used,
+                                   "" if used == 1 else "s")}
+    oracle.set_threads(want)
+    main = runs.get("all") or runs.get("one")
+    model = host["lscpu_model"] or host["cpuinfo_model"] or platform.processor() or "unknown"
+    return {"value": main["value"], "unit": main["unit"], "cores": main["cores"], "kind": "oracle",
+            "sample": main["sample"] + " of " + model + ", %.1f s" % main["seconds"],
+            "single_core": runs.get("one"), "build": "gcc -O3 -march=native -fopenmp (%s)" % os.path.basename(lib),
+            "host": host}
 
 
 def batch_comparison() -> dict:
@@ -248,16 +289,51 @@ def bench_reach(args) -> int:
     return 0
 
 
+def serving_block(rates, count: int, budget: int) -> dict:
+    """Continuous batching under Poisson arrivals of the mixed serving
+    requests, against the same arrivals served one plan at a time, per
+    rate; admission by the 25 B/pose formula against `budget` bytes."""
+    from paper_2306_01301_amd import scenes, serving
+
+    reqs = scenes.serving_requests(count=count)
+    warm = serving.Server(budget, max_live=64)
+    warm.run(reqs[:4], [0.0] * 4)
+    warm.close()
+    per_rate = []
+    for rate in rates:
+        arr = scenes.poisson_arrivals(1306 + int(rate), rate, len(reqs))
+        srv = serving.Server(budget, max_live=64)
+        res = srv.run(reqs, arr)
+        srv.close()
+        s = serving.latency_summary(res)
+        s["rate"] = rate
+        s["peak_admitted_bytes"] = srv.peak_held
+        s["admission_waits"] = srv.admission_waits
+        s["one_plan_at_a_time"] = serving.latency_summary(serving.run_fifo(reqs, arr))
+        per_rate.append(s)
+        print(json.dumps({"serving_rate": rate, "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"],
+                          "fifo_p99_ms": s["one_plan_at_a_time"]["p99_ms"]}), file=sys.stderr, flush=True)
+    return {"workload": "serving_requests", "requests_per_rate": len(reqs), "hbm_budget_bytes": budget,
+            "admission": "25 B/pose (3 vertices x 2 gears x 4 B + 1 B collision)", "rates": per_rate}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="maze_512")
-    ap.add_argument("--cpu-cycles", type=int, default=20, help="oracle cycles timed for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-cycles", type=int, default=20,
+                    help="oracle cycles timed on all host CPUs for cpu_baseline (0: skip the CPU baseline)")
+    ap.add_argument("--cpu-cycles-one", type=int, default=2, help="oracle cycles timed on one core")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of 1 GiB (counter calibration)")
     ap.add_argument("--skip-batch", action="store_true", help="skip the batched-vs-single comparison")
+    ap.add_argument("--skip-serving", action="store_true", help="skip the serving block")
+    ap.add_argument("--skip-check", action="store_true", help="skip the check against sweep_n_turns")
+    ap.add_argument("--serve-rates", default="20,200", help="serving block: Poisson rates in plans/s")
+    ap.add_argument("--serve-requests", type=int, default=300, help="serving block: requests per rate")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="serving block: admission budget")
     ap.add_argument("--rates", default="10,20,50,100,200,500",
                     help="serving workload: Poisson arrival rates in plans/s")
     ap.add_argument("--requests", type=int, default=48, help="serving workload: requests per rate")
@@ -294,9 +370,14 @@ def main() -> int:
     stream = p.stream
     n_sched = len(sc.schedule)
     passes = planner.schedule_passes(sc.schedule, 0, n_sched * sc.n_cycles)
+    family = p.tables()["I"]
+    n_planes = {"straight_x": int(np.sum(family == 0)), "straight_y": int(np.sum(family == 1))}
+    N2 = sc.nx * sc.nx
 
     def one_plan(events):
-        """One step.  events: list to append (tag, event) pairs to, or None."""
+        """One step.  events: list to append (tag, event) pairs to, or None.
+        A straight pass is its two kernels (y-major planes, then x-major
+        planes), with an event after each."""
         def mark(tag):
             if events is not None:
                 e = torch.cuda.Event(enable_timing=True)
@@ -307,9 +388,15 @@ def main() -> int:
         mark("render")
         p.sweep(sc.start, 0)  # init: V = INF, V(start) = 0
         mark("init")
-        for a, b in passes:  # the passes sweep_n_turns runs, one event each
-            p.sweep_pass(a, b)
-            mark((a, b))
+        for a, b in passes:  # the passes sweep_n_turns runs
+            if kernel_kind(a, b) == "straight":
+                p.sweep_straight_family(a, 1)
+                mark("straight_y")
+                p.sweep_straight_family(a, 0)
+                mark("straight_x")
+            else:
+                p.sweep_pass(a, b)
+                mark(kernel_kind(a, b))
         path = p.extract(sc.goal, sc.goal_radius, sc.w_xy, sc.w_t)
         mark("extract")
         return path
@@ -331,44 +418,66 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    # per-stage and per-pass durations from the events (plan's stream)
+    # per-stage and per-kernel durations from the events (plan's stream)
     stage = {"render": [], "init": [], "sweeps": [], "extract": []}
-    kinds = {k: [] for k in PASS_KINDS}
+    kinds = {k: [] for k in KERNELS}
     for ev in step_events:
         t = {}
-        prev = None
         sweeps = 0.0
-        for tag, e in ev:
-            if prev is not None:
-                dt = prev[1].elapsed_time(e)
-                if tag in ("render", "init", "extract"):
-                    t[tag] = dt
-                else:
-                    sweeps += dt
-                    kinds[pass_kind(*tag)].append(dt)
-            prev = (tag, e)
+        for (_, ea), (tag, eb) in zip(ev[:-1], ev[1:]):
+            dt = ea.elapsed_time(eb)
+            if tag in ("render", "init", "extract"):
+                t[tag] = dt
+            else:
+                sweeps += dt
+                kinds[tag].append(dt)
         for k in ("render", "init", "extract"):
             stage[k].append(t[k])
         stage["sweeps"].append(sweeps)
 
+    check = None
+    if not args.skip_check:
+        # the timed steps drove the passes one by one: the last step's value
+        # volume and plan must equal what sweep_n_turns (captured cycle
+        # graphs) leaves, which the parity tests compare with the oracle
+        timed_V = p.value.clone()
+        p.sweep(sc.start, sc.n_cycles)
+        ref = p.extract(sc.goal, sc.goal_radius, sc.w_xy, sc.w_t)
+        same_V = bool(torch.equal(p.value, timed_V))
+        same_plan = (path.best, path.value, path.score, path.steps) == (ref.best, ref.value, ref.score, ref.steps)
+        if not (same_V and same_plan):
+            print("bench: the timed passes disagree with sweep_n_turns (value volume equal: %s, plan equal: %s)"
+                  % (same_V, same_plan), file=sys.stderr)
+            return 1
+        check = "value volume and plan of the timed passes equal to sweep_n_turns"
+        del timed_V
+
     updates = sizing.pose_updates(sc.nx, sc.nt, sc.n_cycles, n_sched)
     ms_per_step = 1000.0 * wall / args.steps
-    # every pass reads V and the codes and writes V once per pose
-    alg_bytes = BYTES_PER_UPDATE * sc.n_poses
-    per_kind = {}
+    traffic = measured_traffic()
+    per_kernel = {}
+    phys_bytes_step = 0.0
     for k, v in kinds.items():
-        if v:
-            avg = float(np.mean(v))
-            per_kind[k] = {"passes_per_step": len(v) // args.steps, "avg_ms": avg,
-                           "ms_per_step": float(np.sum(v)) / args.steps,
-                           "GB_per_s": alg_bytes / (avg * 1e-3) / 1e9,
-                           "updates_per_pose": 2 if k == "fused_turn" else 1, "kernel": PASS_KINDS[k]}
-    # the dominant kernel: a straight pass is two kernels (y-major and x-major
-    # planes), each with a smaller share than a pass kind of one kernel
-    dom = max((k for k in per_kind if k != "straight"), key=lambda k: per_kind[k]["ms_per_step"])
-    achieved = per_kind[dom]["GB_per_s"]
+        if not v:
+            continue
+        avg = float(np.mean(v))
+        planes = n_planes.get(k, sc.nt)
+        nbytes = BYTES_PER_UPDATE * N2 * planes  # read V, read code, write V once per pose of the launch
+        per_step = len(v) // args.steps
+        phys_bytes_step += nbytes * per_step
+        gbs = nbytes / (avg * 1e-3) / 1e9
+        ups = 2 if k == "fused_turn" else 1
+        tr = traffic.get(k)
+        per_kernel[k] = {"kernel": KERNELS[k], "launches_per_step": per_step, "avg_us": avg * 1e3,
+                         "ms_per_step": float(np.sum(v)) / args.steps, "planes": planes,
+                         "bytes_per_launch": nbytes, "GB_per_s": gbs, "frac_physical": gbs / HBM_PEAK_GBS,
+                         "updates_per_pose": ups, "frac_update_equivalent": ups * gbs / HBM_PEAK_GBS,
+                         "traffic_bytes_per_launch": tr, "traffic_ratio": (tr / nbytes) if tr else None}
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
     sweep_ms = float(np.median(stage["sweeps"]))
+    sweep_sum_ms = float(np.mean(stage["sweeps"]))
     lat_ms = np.array(lat) * 1000.0
+    d = per_kernel[dom]
     out = {
         "metric": METRIC,
         "value": updates / (ms_per_step * 1e-3),
@@ -391,17 +500,29 @@ def main() -> int:
                        "batched": None},
         "stages_ms": {k: float(np.median(v)) for k, v in stage.items()},
         "plan": {"maneuvers": len(path.steps), "cost_cells": path.value / 1024.0, "best": list(path.best)},
-        "roofline": {"kernel": PASS_KINDS[dom], "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom), "bytes_per_launch_algorithmic": alg_bytes,
-                     "avg_launch_ms": per_kind[dom]["avg_ms"], "launches_timed": len(kinds[dom]),
-                     "passes": per_kind},
+        "check": check,
+        "roofline": {"kernel": d["kernel"], "bound": "hbm", "achieved": d["GB_per_s"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": d["frac_physical"], "traffic": d["traffic_bytes_per_launch"],
+                     "bytes_per_launch_algorithmic": d["bytes_per_launch"], "avg_launch_us": d["avg_us"],
+                     "launches_timed": len(kinds[dom]),
+                     "frac_reading": "physical: 9 B per pose each launch reads and writes once (a fused turn "
+                                     "launch relaxes every pose twice for those 9 B)",
+                     "kernels": per_kernel,
+                     "whole_sweep": {"ms": sweep_sum_ms,
+                                     "physical_bytes": phys_bytes_step,
+                                     "frac_physical": phys_bytes_step / (sweep_sum_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                     "update_equivalent_bytes": BYTES_PER_UPDATE * updates,
+                                     "frac_update_equivalent": BYTES_PER_UPDATE * updates / (sweep_sum_ms * 1e-3)
+                                     / 1e9 / HBM_PEAK_GBS}},
     }
     p.close()
     if not args.skip_batch:
         out["latency_ms"]["batch_64"] = batch_comparison()
+    if not args.skip_serving:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        out["serving"] = serving_block(rates, args.serve_requests, int(args.serve_budget_gib * (1 << 30)))
     if args.cpu_cycles > 0:
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_cycles)
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_cycles, args.cpu_cycles_one)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

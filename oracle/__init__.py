@@ -33,15 +33,30 @@ DEFAULT_SCHEDULE = [LF, SF, RB, RF, SB, LB]
 OK, EINVAL, ENOMEM, ESTART, EUNREACH, ECAP = 0, -1, -2, -4, -5, -6
 
 
-def build(force: bool = False) -> str:
-    """Compiles the oracle shared library in place (gcc, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+_LIB_NATIVE = os.path.join(_HERE, "libnhp_oracle_native.so")
+_active = _LIB
+
+
+def build(force: bool = False, native: bool = False) -> str:
+    """Compiles the oracle shared library in place (gcc, OpenMP).
+
+    native: builds a second copy with -O3 -march=native for the host it runs
+    on (always rebuilt, since the host may differ from the one that built
+    the first) and makes the module use it from then on; the timing
+    baseline runs on it.  Floating-point contraction stays off, so the
+    tables come out the same either way."""
+    global _active, _lib
+    target = _LIB_NATIVE if native else _LIB
+    opt = ["-O3", "-march=native", "-ffp-contract=off"] if native else ["-O2"]
+    if force or native or not os.path.exists(target) or os.path.getmtime(target) < os.path.getmtime(_SRC):
+        tmp = target + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-Wall", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"]
+            ["gcc"] + opt + ["-std=c99", "-Wall", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"]
         )
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, target)
+    if native and _active != target:
+        _active, _lib = target, None
+    return target
 
 
 class _Problem(ctypes.Structure):
@@ -74,9 +89,9 @@ _lib = None
 def _L():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_active):
             build()
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(_active)
         P = ctypes.POINTER
         vp = ctypes.c_void_p
         i32 = ctypes.c_int32

@@ -178,6 +178,8 @@ class Server:
         self.digests = digests
         self.streams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
         self.batches = [P.Batch(max_live, stream=st) for st in self.streams]
+        self.peak_held = 0        # largest admitted footprint at once (bytes)
+        self.admission_waits = 0  # ticks on which an arrived request waited for memory
 
     def run(self, scs: Sequence, arrivals: Sequence[float]) -> List[Result]:
         order = np.argsort(np.asarray(arrivals), kind="stable")
@@ -196,9 +198,11 @@ class Server:
                 sc = scs[k]
                 need = footprint_bytes(sc, self.rule)
                 if held + need > self.budget and (live or fresh):
+                    self.admission_waits += 1
                     break
                 pending.pop(0)
                 held += need
+                self.peak_held = max(self.peak_held, held)
                 cls = 1 if sc.n_poses >= LARGE_POSES else 0
                 st = self.streams[cls]
                 pl = P.planner_for(sc, stream=st)
