@@ -9,12 +9,10 @@ continuous-batching server.
   arrival order through the single-plan entry points.
 * `Server`: requests arrive over time (e.g. Poisson); a request is admitted
   when its HBM footprint fits the budget, its map and volumes then stay on
-  the device until it completes.  Small and large plans run in two classes
-  on two streams so their launches overlap; within a class every tick
-  advances every admitted plan by a number of sweeps inversely proportional
-  to its size (one batch_advance call, shared launches); plans that finish
-  their sweeps are extracted together and release their memory, and
-  requests that arrived meanwhile are admitted at the next tick.
+  the device until it completes.  Admission (plan, image, rendering, init),
+  sweeps (shared launches of the live plans picked per tick, shortest
+  remaining work first with aging) and extraction run on three streams, so
+  neither admission nor extraction waits for queued sweeps.
 
 Host code only (scheduling and bookkeeping); all planning work runs in the
 HIP library.
@@ -147,129 +145,237 @@ class _Live:
     scene: object
     planner: P.Planner
     image: torch.Tensor
-    total: int
-    cls: int = 0
-    done: int = 0
-    per_tick: int = 1
+    total: int              # sweeps of the plan
+    arrival: float
+    done: int = 0           # sweeps enqueued so far
     footprint: int = 0
+    finish_event: Optional[torch.cuda.Event] = None
+
+    @property
+    def remaining_updates(self) -> int:
+        return (self.total - self.done) * self.scene.n_poses
 
 
-LARGE_POSES = 1 << 25  # plans at least this large go to the large class
-LARGE_AT_ONCE = 1      # large plans advanced per tick (1: shortest remaining work first, one at a time)
+# Scheduling of a tick (measured on the MI355X; see tick_plan).
+FILL_POSES = 64 << 20    # poses a tick's passes cover together before it stops adding plans
+TICK_POSES = 1 << 30     # pose updates each selected plan gets per tick (at least one pass)
+AGING = 1.0              # seconds of expected work a second of waiting is worth
+UPDATE_RATE = 6.0e11     # pose updates per second of the sweep kernels, for the expected-work estimate
+MAX_QUEUED_TICKS = 2     # ticks enqueued ahead of the GPU
+ADMIT_PER_TICK = 4       # requests per hand-over to the admission thread
+
+
+def tick_plan(live: Sequence[_Live], now: float, fill_poses: int = FILL_POSES, tick_poses: int = TICK_POSES,
+              aging: float = AGING, rate: float = UPDATE_RATE):
+    """Which live plans advance this tick, and by how many sweeps.
+
+    Plans are taken in order of expected remaining work minus `aging` times
+    their time in the system (shortest remaining work first, with older
+    requests moving up so that a large request is not passed over
+    indefinitely), until their passes together cover `fill_poses` poses (so
+    every shared launch has enough tiles to fill the GPU).  Each selected
+    plan runs whole passes worth about `tick_poses` pose updates (at least
+    one pass; a tick ends on a pass boundary so turn pairs stay fused).
+    Returns [(plan, sweeps)]."""
+    runnable = [l for l in live if l.done < l.total]
+    runnable.sort(key=lambda l: (l.remaining_updates / rate - aging * (now - l.arrival), l.arrival, l.k))
+    out, covered = [], 0
+    for l in runnable:
+        if covered >= fill_poses:
+            break
+        want = max(1, int(round(tick_poses / l.scene.n_poses)))
+        passes = P.schedule_passes(l.scene.schedule, l.done, l.total - l.done)[:want]
+        out.append((l, sum(1 if b < 0 else 2 for _, b in passes)))
+        covered += l.scene.n_poses
+    return out
 
 
 class Server:
     """Continuous batching over requests that arrive over time.
 
-    Plans are split into two size classes, each with its own stream and
-    batch, so that the many short passes of small plans run on the GPU at
-    the same time as the long passes of large plans instead of waiting
-    between them.  Every tick advances each live small plan, and the large
-    plan(s) with the least remaining work (LARGE_AT_ONCE), by a number of
-    passes inversely proportional to its size within its class (one
-    batch_advance call per class); finished plans are extracted together and
-    release their memory, and requests that arrived meanwhile are admitted at
-    the next tick."""
+    Three streams and an admission thread keep the GPU fed:
+      * admission: arrived requests whose HBM footprint fits the budget are
+        handed, most urgent first (the tick priority below), to a worker
+        thread that makes their plans, uploads their images, renders their
+        obstacle volumes and initialises their value volumes on its own
+        stream, so neither this host work nor the synchronisations it needs
+        hold up the sweeps (the library's calls release the interpreter
+        lock while they run);
+      * sweeps: each tick, the plans tick_plan picks advance together in
+        shared launches (batch_advance); at most MAX_QUEUED_TICKS ticks are
+        enqueued ahead of the GPU;
+      * extraction: a plan whose last sweep has completed (its event) gets
+        its goal search and back-tracking here, with every other finished
+        plan, and releases its memory.
+    Requests that arrive meanwhile are admitted as memory and slots free."""
 
-    def __init__(self, hbm_budget: int, max_live: int = 64, rule: str = "formula", digests: bool = False):
+    def __init__(self, hbm_budget: int, max_live: int = 64, rule: str = "formula", digests: bool = False,
+                 fill_poses: int = FILL_POSES, tick_poses: int = TICK_POSES, aging: float = AGING,
+                 admit_per_tick: int = ADMIT_PER_TICK):
         self.budget = int(hbm_budget)
         self.max_live = int(max_live)
         self.rule = rule
         self.digests = digests
-        self.streams = [torch.cuda.Stream(), torch.cuda.Stream()]  # default priority
-        self.batches = [P.Batch(max_live, stream=st) for st in self.streams]
+        self.fill_poses, self.tick_poses, self.aging = int(fill_poses), int(tick_poses), float(aging)
+        self.admit_per_tick = int(admit_per_tick)  # requests per hand-over to the admission thread
+        self.device = torch.cuda.current_device()
+        # default priority for every stream
+        self.s_admit, self.s_sweep, self.s_extract = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+        self.b_admit = P.Batch(max_live, stream=self.s_admit)
+        self.b_sweep = P.Batch(max_live, stream=self.s_sweep)
+        self.b_extract = P.Batch(max_live, stream=self.s_extract)
         self.peak_held = 0        # largest admitted footprint at once (bytes)
         self.admission_waits = 0  # ticks on which an arrived request waited for memory
+        self.ticks = 0
+        self.host_s = {"admit": 0.0, "tick": 0.0, "extract": 0.0, "wait": 0.0}  # main-thread host time per phase
+
+    def _admission(self, inbox: "queue.Queue", outbox: "queue.Queue") -> None:
+        """Worker thread: plans, images, rendering and init of handed-over requests."""
+        torch.cuda.set_device(self.device)
+        while True:
+            job = inbox.get()
+            if job is None:
+                return
+            try:
+                fresh = []
+                with torch.cuda.stream(self.s_admit):
+                    for k, sc, arrival, need in job:
+                        pl = P.planner_for(sc, stream=self.s_admit)
+                        img = torch.from_numpy(np.ascontiguousarray(sc.image)).cuda()
+                        fresh.append(_Live(k, sc, pl, img, sc.n_cycles * len(sc.schedule), arrival, footprint=need))
+                    planners = [f.planner for f in fresh]
+                    self.b_admit.render(planners, [f.image for f in fresh], [f.scene.vehicle for f in fresh])
+                    self.b_admit.init(planners, [f.scene.start for f in fresh])
+                    ready = torch.cuda.Event()
+                    ready.record(self.s_admit)
+                for f in fresh:
+                    f.finish_event = ready if f.total == 0 else None
+                outbox.put((fresh, ready))
+            except BaseException as e:  # handed to the main thread, which raises it
+                outbox.put((e, None))
 
     def run(self, scs: Sequence, arrivals: Sequence[float]) -> List[Result]:
-        order = np.argsort(np.asarray(arrivals), kind="stable")
+        import queue
+        import threading
+
         results = [Result(sc.name, float(a)) for sc, a in zip(scs, arrivals)]
-        pending = [int(k) for k in order]
-        live: List[_Live] = []
+        pending = [int(k) for k in np.argsort(np.asarray(arrivals), kind="stable")]
+        work = {k: sizing.pose_updates(scs[k].nx, scs[k].nt, scs[k].n_cycles, len(scs[k].schedule)) / UPDATE_RATE
+                for k in pending}
+        live: List[_Live] = []       # admitted and ready: sweeps still to enqueue or to complete
+        admitting = 0                # handed to the admission thread, not back yet
+        queued: List[torch.cuda.Event] = []  # one per enqueued tick
         held = 0
+        inbox, outbox = queue.Queue(), queue.Queue()
+        worker = threading.Thread(target=self._admission, args=(inbox, outbox), daemon=True)
+        worker.start()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        while pending or live:
-            now = time.perf_counter() - t0
-            # admit arrived requests while memory and slots allow (in arrival order)
-            fresh: List[_Live] = []
-            while pending and results[pending[0]].arrival <= now and len(live) + len(fresh) < self.max_live:
-                k = pending[0]
-                sc = scs[k]
-                need = footprint_bytes(sc, self.rule)
-                if held + need > self.budget and (live or fresh):
-                    self.admission_waits += 1
-                    break
-                pending.pop(0)
-                held += need
-                self.peak_held = max(self.peak_held, held)
-                cls = 1 if sc.n_poses >= LARGE_POSES else 0
-                st = self.streams[cls]
-                pl = P.planner_for(sc, stream=st)
-                with torch.cuda.stream(st):
-                    img = torch.from_numpy(np.ascontiguousarray(sc.image)).cuda()
-                fresh.append(_Live(k, sc, pl, img, sc.n_cycles * len(sc.schedule), cls=cls, footprint=need))
-                results[k].admitted = time.perf_counter() - t0
-            for cls in (0, 1):
-                new = [f for f in fresh if f.cls == cls]
-                if new:
-                    b = self.batches[cls]
-                    b.render([f.planner for f in new], [f.image for f in new], [f.scene.vehicle for f in new])
-                    b.init([f.planner for f in new], [f.scene.start for f in new])
-            live.extend(fresh)
-            if not live:
-                # idle until the next arrival
-                wait = results[pending[0]].arrival - (time.perf_counter() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 0.01))
-                continue
-            finished: List[_Live] = []
-            for cls in (0, 1):
-                mine = [l for l in live if l.cls == cls]
-                if cls == 1:
-                    # large plans: the ones with the least remaining work first
-                    # (shortest remaining work keeps the mean latency low),
-                    # LARGE_AT_ONCE at a time so they do not slow each other down
-                    mine.sort(key=lambda l: (l.total - l.done) * l.scene.n_poses)
-                    mine = mine[:LARGE_AT_ONCE]
-                if not mine:
+        clock = time.perf_counter
+        try:
+            while pending or live or admitting:
+                now = clock() - t0
+                h0 = clock()
+                # ---- admission: arrived requests, most urgent first (expected
+                # work minus aging), memory and slots permitting ----
+                arrived = [k for k in pending if results[k].arrival <= now]
+                arrived.sort(key=lambda k: (work[k] - self.aging * (now - results[k].arrival), results[k].arrival, k))
+                job = []
+                if admitting < 2 * self.admit_per_tick:
+                    for k in arrived:
+                        if len(live) + admitting + len(job) >= self.max_live or len(job) >= self.admit_per_tick:
+                            break
+                        sc = scs[k]
+                        need = footprint_bytes(sc, self.rule)
+                        if held + need > self.budget and (live or admitting or job):
+                            self.admission_waits += 1
+                            break
+                        pending.remove(k)
+                        held += need
+                        self.peak_held = max(self.peak_held, held)
+                        job.append((k, sc, results[k].arrival, need))
+                        results[k].admitted = clock() - t0
+                if job:
+                    inbox.put(job)
+                    admitting += len(job)
+                got = False
+                while True:
+                    try:
+                        fresh, ready = outbox.get_nowait()
+                    except queue.Empty:
+                        break
+                    if isinstance(fresh, BaseException):
+                        raise fresh
+                    got = True
+                    self.s_sweep.wait_event(ready)  # the sweeps of these plans come after their init
+                    for f in fresh:
+                        f.planner.set_stream(self.s_sweep)
+                    live.extend(fresh)
+                    admitting -= len(fresh)
+                h1 = clock()
+                self.host_s["admit"] += h1 - h0
+                # ---- one tick of sweeps ----
+                queued = [e for e in queued if not e.query()]
+                picked = tick_plan(live, now, self.fill_poses, self.tick_poses, self.aging) \
+                    if len(queued) < MAX_QUEUED_TICKS else []
+                if picked:
+                    self.b_sweep.advance([l.planner for l, _ in picked], [l.done for l, _ in picked],
+                                         [n for _, n in picked])
+                    ev = torch.cuda.Event()
+                    ev.record(self.s_sweep)
+                    queued.append(ev)
+                    self.ticks += 1
+                    for l, n in picked:
+                        l.done += n
+                        if l.done >= l.total:
+                            l.finish_event = ev
+                h2 = clock()
+                self.host_s["tick"] += h2 - h1
+                # ---- extraction of plans whose sweeps have completed ----
+                done = [l for l in live if l.finish_event is not None and l.finish_event.query()]
+                if not done and not picked and not got and not job:
+                    if queued:
+                        queued[0].synchronize()  # nothing to do until the oldest enqueued tick completes
+                    elif admitting:
+                        try:  # wait for the admission thread
+                            outbox.put(outbox.get(timeout=0.005))
+                        except queue.Empty:
+                            pass
+                    elif pending:
+                        wait = min(results[k].arrival for k in pending) - (clock() - t0)
+                        if wait > 0:
+                            time.sleep(min(wait, 0.005))
+                    self.host_s["wait"] += clock() - h2
                     continue
-                # passes per tick: inversely proportional to the plan's size;
-                # a tick ends on a pass boundary so that turn pairs stay fused
-                biggest = max(l.scene.n_poses for l in mine)
-                for l in mine:
-                    want = max(1, int(round(biggest / l.scene.n_poses)))
-                    passes = P.schedule_passes(l.scene.schedule, l.done, l.total - l.done)[:want]
-                    l.per_tick = sum(1 if b < 0 else 2 for _, b in passes)
-                self.batches[cls].advance([l.planner for l in mine], [l.done for l in mine],
-                                          [l.per_tick for l in mine])
-                for l in mine:
-                    l.done += l.per_tick
-                finished += [l for l in mine if l.done >= l.total]
-            for cls in (0, 1):
-                done = [l for l in finished if l.cls == cls]
-                if not done:
-                    continue
-                paths = self.batches[cls].extract([l.planner for l in done], [l.scene.goal for l in done],
-                                                  [l.scene.goal_radius for l in done], [l.scene.w_xy for l in done],
-                                                  [l.scene.w_t for l in done])
-                t = time.perf_counter() - t0
-                for l, path in zip(done, paths):
-                    r = results[l.k]
-                    r.finished = t
-                    if isinstance(path, int):
-                        r.status = path
-                    else:
-                        r.path = path
-                    if self.digests:
-                        r.value_digest = _digest(l.planner)
-                    l.planner.close()
-                    held -= l.footprint
-            live = [l for l in live if l.done < l.total]
+                if done:
+                    for l in done:
+                        self.s_extract.wait_event(l.finish_event)
+                        l.planner.set_stream(self.s_extract)  # its own work (digest, destroy) waits on this stream
+                    paths = self.b_extract.extract([l.planner for l in done], [l.scene.goal for l in done],
+                                                   [l.scene.goal_radius for l in done],
+                                                   [l.scene.w_xy for l in done], [l.scene.w_t for l in done])
+                    t = clock() - t0
+                    for l, path in zip(done, paths):
+                        r = results[l.k]
+                        r.finished = t
+                        if isinstance(path, int):
+                            r.status = path
+                        else:
+                            r.path = path
+                        if self.digests:
+                            r.value_digest = _digest(l.planner)
+                        l.planner.close()
+                        held -= l.footprint
+                    gone = set(id(l) for l in done)
+                    live = [l for l in live if id(l) not in gone]
+                    self.host_s["extract"] += clock() - h2
+        finally:
+            inbox.put(None)
+            worker.join()
         return results
 
     def close(self) -> None:
-        for b in self.batches:
+        for b in (self.b_admit, self.b_sweep, self.b_extract):
             b.close()
 
 

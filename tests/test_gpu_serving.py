@@ -69,28 +69,28 @@ def _oracle_key(sc):
     return (0, digest, (best, value, score), [(s.maneuver, s.steps, s.frm, s.to, s.cost) for s in steps])
 
 
-def test_served_results_match_oracle(monkeypatch):
-    """Small and large requests at once (the large class lowered to 2^22
-    poses so both classes and both streams run together, with a 512-side
-    request among the large), admitted under a budget that makes requests
-    wait: every served result equals the oracle's."""
+def test_served_results_match_oracle():
+    """Small and large requests (a 512-side request among them) admitted
+    under a budget that makes requests wait, with ticks small enough that
+    plans are picked in turn (shortest remaining work first) and share
+    launches at different points of their schedules: every served result
+    equals the oracle's."""
     import os
 
     import oracle
 
     oracle.set_threads(min(16, os.cpu_count() or 1))
-    monkeypatch.setattr(serving, "LARGE_POSES", 1 << 22)
     rng = np.random.default_rng(78)
     reqs = [scenes.random_instance(rng, sides=(64, 128), thetas=(64, 128), n_range=(2, 5), name="s%02d" % k)
             for k in range(6)]
     reqs.insert(1, scenes.random_instance(rng, sides=(512,), thetas=(128,), n_range=(3, 3), name="L512"))
     reqs.insert(4, scenes.random_instance(rng, sides=(256,), thetas=(256,), n_range=(3, 3), name="L256"))
-    assert sum(sc.n_poses >= serving.LARGE_POSES for sc in reqs) == 2
-    arrivals = scenes.poisson_arrivals(6, 200.0, len(reqs))
-    budget = serving.footprint_bytes(reqs[1]) + 2 * max(serving.footprint_bytes(sc) for sc in reqs[2:])
-    srv = serving.Server(budget, max_live=8, digests=True)
+    arrivals = [0.0] * len(reqs)  # all at once: the budget below admits the 512-side plan and one more at most
+    budget = serving.footprint_bytes(reqs[1]) + min(serving.footprint_bytes(sc) for sc in reqs)
+    srv = serving.Server(budget, max_live=8, digests=True, fill_poses=1 << 22, tick_poses=1 << 21)
     served = srv.run(reqs, arrivals)
     srv.close()
+    assert srv.admission_waits > 0 and srv.ticks > len(reqs)
     for sc, r in zip(reqs, served):
         print("request %s %dx%dx%d N=%d: oracle" % (sc.name, sc.nx, sc.nx, sc.nt, sc.n_cycles), flush=True)
         assert _key(r) == _oracle_key(sc), sc.name
