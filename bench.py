@@ -154,6 +154,9 @@ def batch_comparison() -> dict:
     updates = sum(sizing.pose_updates(s.nx, s.nt, s.n_cycles, len(s.schedule)) for s in reqs)
     serving.run_batched(reqs[:8])  # warm-up
     serving.run_single(reqs[:8])
+    warm = serving.Server(1 << 60, max_live=8)
+    warm.run(reqs[:8], [0.0] * 8)
+    warm.close()
     out = {"workload": "batch_64", "plans": len(reqs), "pose_updates": updates}
 
     def continuous(rs):
@@ -289,6 +292,39 @@ def bench_reach(args) -> int:
     return 0
 
 
+def bench_batch_modes(args) -> int:
+    """batch_64 once in one mode (--mode batched|continuous|single), after a
+    warm-up and a marker kernel (a fill of 7777 words), for kernel traces:
+    python -m paper_2306_01301_amd.profsum gaps DIR reads the trace after the
+    marker."""
+    import torch
+
+    from paper_2306_01301_amd import scenes, serving
+
+    reqs = scenes.batch_64()
+    serving.run_batched(reqs[:8])
+    serving.run_single(reqs[:8])
+    warm = serving.Server(1 << 60, max_live=8)
+    warm.run(reqs[:8], [0.0] * 8)
+    warm.close()
+    torch.cuda.synchronize()
+    torch.full((7777,), 7, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if args.mode == "batched":
+        res = serving.run_batched(reqs)
+    elif args.mode == "single":
+        res = serving.run_single(reqs)
+    else:
+        srv = serving.Server(1 << 60, max_live=len(reqs))
+        res = srv.run(reqs, [0.0] * len(reqs))
+        srv.close()
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "batch_64", "mode": args.mode, "wall_ms": (time.perf_counter() - t0) * 1e3,
+                      **serving.latency_summary(res)}), flush=True)
+    return 0
+
+
 def serving_block(rates, count: int, budget: int) -> dict:
     """Continuous batching under Poisson arrivals of the mixed serving
     requests, against the same arrivals served one plan at a time, per
@@ -334,6 +370,7 @@ def main() -> int:
     ap.add_argument("--serve-rates", default="20,200", help="serving block: Poisson rates in plans/s")
     ap.add_argument("--serve-requests", type=int, default=300, help="serving block: requests per rate")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="serving block: admission budget")
+    ap.add_argument("--mode", default="batched", help="batch_64 workload: batched, continuous or single")
     ap.add_argument("--rates", default="10,20,50,100,200,500",
                     help="serving workload: Poisson arrival rates in plans/s")
     ap.add_argument("--requests", type=int, default=48, help="serving workload: requests per rate")
@@ -357,6 +394,8 @@ def main() -> int:
         return bench_serving(args)
     if args.workload.startswith("reach"):
         return bench_reach(args)
+    if args.workload == "batch_64":
+        return bench_batch_modes(args)
     sc = scenes.WORKLOADS[args.workload]()
     if args.calibrate_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")

@@ -307,7 +307,11 @@ int batch_init(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* starts_
 int batch_step(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* steps, uint32_t n);
 
 /* Several ticks at once: plan k runs its sweeps steps[k] .. steps[k] +
- * counts[k] - 1 (counts[k] = 0: none).  Consecutive turn sweeps on the same
+ * counts[k] - 1 (counts[k] = 0: none).  A call whose launches repeat those
+ * of an earlier call on this batch (the same plans at the same points of
+ * their schedules, under the same knobs) is captured into a HIP graph the
+ * second time and replayed after that; the batch keeps up to 16 such graphs,
+ * each with its own device copy of its job table.  Consecutive turn sweeps on the same
  * circles in opposite directions (RB then RF, LB then LF, and the reverse
  * orders) share one pass over the volume, with the same result as two
  * batch_step calls; pass t of every plan goes into shared launches (at most
@@ -315,9 +319,11 @@ int batch_step(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* steps, 
 int batch_advance(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* steps, const uint32_t* counts,
                   uint32_t n);
 
-/* batch_init, then batch_advance from step 0 by n_cycles[k] * n_schedule
- * sweeps: plan k ends with n_cycles[k] cycles, as sweep_n_turns would leave
- * it. */
+/* batch_init, then one batch_advance per cycle (the plans with cycles
+ * left, each with the passes sweep_n_turns runs: a cycle's last sweep shares
+ * a pass with the next cycle's first when they fuse): plan k ends with
+ * n_cycles[k] cycles, as sweep_n_turns would leave it.  Cycles that repeat
+ * the launches of an earlier one replay them from a captured graph. */
 int batch_sweep(nhp_batch* batch, nhp_plan* const* plans, const uint32_t* starts_ijt,
                 const uint32_t* n_cycles, uint32_t n);
 
@@ -340,6 +346,22 @@ int batch_extract(nhp_batch* batch, nhp_plan* const* plans, uint32_t n, const ui
  * the choice they captured.  Every valid choice gives identical results and
  * only changes speed (the autotuner measures them).  Errors: NHP_EINVAL. */
 int nhp_set_section_steps(uint32_t curve_len, uint32_t steps);
+
+/* Launch-shape knobs of the sweep kernels, process-wide, for the autotuner:
+ * 0 restores the built-in choice.  Every setting gives identical results and
+ * only changes speed.  Plans that already captured their cycle graph keep
+ * the launches they captured. */
+enum nhp_knob {
+  NHP_KNOB_ROW_WG_PER_CU = 0,    /* workgroups per compute unit that the row sweep launches keep resident, 1..8 */
+  NHP_KNOB_XMAJOR_WG_PER_CU = 1, /* the same for the x-major straight launches, 1..16 */
+  NHP_KNOB_TILE_ORDER = 2,       /* 1: tiles that share row segments run on one XCD (its L2); 2: launch order */
+  NHP_KNOB_XMAJOR_BUFFERS = 3    /* x-major LDS tiles per workgroup: 2 (the next chunk's loads need no barrier
+                                    after the stores) or 1 (more workgroups fit a compute unit) */
+};
+/* Errors: NHP_EINVAL (unknown knob or value out of range). */
+int nhp_set_knob(uint32_t knob, int32_t value);
+/* The knob's value (0 = built-in), -1 for an unknown knob. */
+int32_t nhp_get_knob(uint32_t knob);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* plan_last_error(void);

@@ -99,6 +99,9 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
+// Tile of workgroup slot b of n: XCD-aware (order 1) or launch order (order 2).
+__device__ __forceinline__ int tile_of(int b, int n, int order) { return order == 2 ? b : xcd_tile(b, n); }
+
 // Value entering this wave's section: the cyclic fixed point (turns) or the
 // composition of the earlier sections from INF (straights).  Sections are
 // visited in increasing order (forward) or decreasing order (the second
@@ -487,23 +490,23 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
 // LDS slot in a spare row, so no lane branches.  The tile is double
 // buffered, so a chunk's stores and the next chunk's loads need no barrier
 // between them.
-template <int Q, int NT>
+template <int Q, int NT, int BUFS>
 struct XShared {
   static constexpr int LINES = 64;
   static constexpr int NW = NT / 64;    // waves
   static constexpr int PITCH = Q + 1;   // odd pitch: lanes reading one column of 64 lines hit 64 banks
   static constexpr int SLOTS = (LINES + 1) * PITCH;  // 64 lines and the spare row
-  uint32_t tV[2][SLOTS];
-  uint8_t tB[2][SLOTS];
+  uint32_t tV[BUFS][SLOTS];
+  uint8_t tB[BUFS][SLOTS];
   uint32_t aggD[NW][64];
   uint32_t aggC[NW][64];
   uint32_t wlut[256];
   int16_t skew[1024];  // B(c, T) of this plane
 };
 
-template <int Q, int NT>
-__device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, XShared<Q, NT>& sh) {
-  using X = XShared<Q, NT>;
+template <int Q, int NT, int BUFS>
+__device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, XShared<Q, NT, BUFS>& sh) {
+  using X = XShared<Q, NT, BUFS>;
   constexpr int LINES = X::LINES, PITCH = X::PITCH, NW = X::NW;
   constexpr int SUB = Q / NW;   // columns per wave
   constexpr int ROWS = NT / Q;  // band rows per load round
@@ -536,7 +539,7 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
 
   uint32_t carry = kInf;  // value carried along line x0 + lane into the chunk
   int buf = 0;
-  for (int k0 = 0; k0 < N; k0 += Q, buf ^= 1) {
+  for (int k0 = 0; k0 < N; k0 += Q, buf = (BUFS == 2) ? (buf ^ 1) : 0) {
     uint32_t* tV = sh.tV[buf];
     uint8_t* tB = sh.tB[buf];
     const int nq = (N - k0) < Q ? (N - k0) : Q;
@@ -556,23 +559,32 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
     // load the band: band row r holds line t = r + bmin - B(c) of column c
     int row = band0 + r0;
     row -= (row >= N) ? N : 0;
-    uint32_t rel = (uint32_t)row * (uint32_t)N + (uint32_t)(col_ok ? my_c : 0);
-    int t = r0 + bmin - my_b;
-    uint32_t lv[ITER], lc[ITER], idx[ITER], slot[ITER];
+    const uint32_t rel0 = (uint32_t)row * (uint32_t)N + (uint32_t)(col_ok ? my_c : 0);
+    const int t0 = r0 + bmin - my_b;
+    uint32_t lv[ITER], lc[ITER];
+    {
+      uint32_t rel = rel0;
+      int t = t0;
 #pragma unroll
-    for (int it = 0; it < ITER; it++) {
-      const bool own = (uint32_t)t < tl;
-      idx[it] = own ? rel : kNoRecord;
-      slot[it] = own ? (uint32_t)(t * PITCH + kk) : spare;
-      lv[it] = buffer_load_u32(bV, idx[it], 0, 0, 0);
-      lc[it] = buffer_load_u8(bB, idx[it], 0, 0, 0);
-      t += ROWS;
-      rel = wrap_col(rel + (uint32_t)(ROWS * N), (int)NN);  // ROWS rows down, wrapping around the plane
+      for (int it = 0; it < ITER; it++) {
+        const uint32_t idx = (uint32_t)t < tl ? rel : kNoRecord;
+        lv[it] = buffer_load_u32(bV, idx, 0, 0, 0);
+        lc[it] = buffer_load_u8(bB, idx, 0, 0, 0);
+        t += ROWS;
+        rel = wrap_col(rel + (uint32_t)(ROWS * N), (int)NN);  // ROWS rows down, wrapping around the plane
+      }
     }
+    {
+      // the slots are recomputed rather than kept from the loads (registers)
+      int t = t0;
+      asm volatile("" : "+v"(t));
 #pragma unroll
-    for (int it = 0; it < ITER; it++) {
-      tV[slot[it]] = lv[it];
-      tB[slot[it]] = (uint8_t)lc[it];
+      for (int it = 0; it < ITER; it++) {
+        const uint32_t slot = (uint32_t)t < tl ? (uint32_t)(t * PITCH + kk) : spare;
+        tV[slot] = lv[it];
+        tB[slot] = (uint8_t)lc[it];
+        t += ROWS;
+      }
     }
     __syncthreads();
 
@@ -607,8 +619,19 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
     __syncthreads();
 
     // store the band back (cells no line owns have no record: dropped)
+    {
+      uint32_t rel = rel0;
+      int t = t0;
+      asm volatile("" : "+v"(t), "+v"(rel));
 #pragma unroll
-    for (int it = 0; it < ITER; it++) buffer_store_u32(tV[slot[it]], bV, idx[it], 0, 0, 0);
+      for (int it = 0; it < ITER; it++) {
+        const bool own = (uint32_t)t < tl;
+        buffer_store_u32(tV[own ? (uint32_t)(t * PITCH + kk) : spare], bV, own ? rel : kNoRecord, 0, 0, 0);
+        t += ROWS;
+        rel = wrap_col(rel + (uint32_t)(ROWS * N), (int)NN);
+      }
+    }
+    if (BUFS == 1) __syncthreads();  // every wave has read the tile before the next chunk writes it
   }
 }
 
@@ -636,54 +659,65 @@ __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepJob job) {
   __shared__ RowShared sh;
   for (int b = blockIdx.x; b < job.blocks; b += gridDim.x) {
     __syncthreads();
-    row_sweep_tile<P, FUSED, GUARD, POW2>(job, xcd_tile(b, job.blocks), sh);
+    row_sweep_tile<P, FUSED, GUARD, POW2>(job, tile_of(b, job.blocks, job.order), sh);
   }
 }
 
 template <int P, bool FUSED, bool GUARD, bool POW2>
 __global__ __launch_bounds__(1024) void row_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs,
-                                                                 int total_blocks) {
+                                                                 int total_blocks, int order) {
   __shared__ RowShared sh;
   for (int b = blockIdx.x; b < total_blocks; b += gridDim.x) {
     __syncthreads();
-    const int t = xcd_tile(b, total_blocks);
+    const int t = tile_of(b, total_blocks, order);
     const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
     const SweepJob job = jobs[j];
     row_sweep_tile<P, FUSED, GUARD, POW2>(job, t - job.first_block, sh);
   }
 }
 
+// Launch-shape knobs (nhp_set_knob; 0 = built-in choice).
+std::atomic<int> g_knob[kKnobs];
+
+int knob(int k, int builtin) {
+  const int v = g_knob[k].load(std::memory_order_relaxed);
+  return v ? v : builtin;
+}
+
 // Resident workgroups for a row launch: 256 CUs times the workgroups of
-// `waves` waves that fit one CU (at most 16 waves per CU at these register
-// counts, 32 for the small sections).
+// `waves` waves that fit one CU (built-in: at most 16 waves per CU at these
+// register counts, 32 for the small sections).
 int row_grid(int blocks, int waves, int P) {
-  const int per_cu = (P >= 32 ? 16 : 32) / waves;
-  const int cap = 256 * (per_cu > 0 ? per_cu : 1);
+  const int builtin = (P >= 32 ? 16 : 32) / waves;
+  const int per_cu = knob(NHP_KNOB_ROW_WG_PER_CU, builtin > 0 ? builtin : 1);
+  const int cap = 256 * per_cu;
   return blocks < cap ? blocks : cap;
 }
 
 // x-major workgroups stay resident too.  A tile's stores read only the LDS
 // band, and the next tile writes its band after the barrier that follows its
 // weight and skew tables, so a wave still storing never sees it overwritten.
-template <int Q, int NT>
+template <int Q, int NT, int BUFS>
 __global__ __launch_bounds__(NT) void xmajor_sweep_kernel(SweepJob job) {
-  __shared__ XShared<Q, NT> sh;
-  for (int b = blockIdx.x; b < job.blocks; b += gridDim.x) xmajor_sweep_tile<Q, NT>(job, xcd_tile(b, job.blocks), sh);
+  __shared__ XShared<Q, NT, BUFS> sh;
+  for (int b = blockIdx.x; b < job.blocks; b += gridDim.x)
+    xmajor_sweep_tile<Q, NT, BUFS>(job, tile_of(b, job.blocks, job.order), sh);
 }
 
 // Resident x-major workgroups: 8 per CU (about what fits at once).
 int xmajor_grid(int blocks) {
-  const int cap = 256 * 8;
+  const int cap = 256 * knob(NHP_KNOB_XMAJOR_WG_PER_CU, 8);
   return blocks < cap ? blocks : cap;
 }
 
-template <int Q, int NT>
-__global__ __launch_bounds__(NT) void xmajor_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs) {
-  __shared__ XShared<Q, NT> sh;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
+template <int Q, int NT, int BUFS>
+__global__ __launch_bounds__(NT) void xmajor_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs,
+                                                                 int order) {
+  __shared__ XShared<Q, NT, BUFS> sh;
+  const int t = tile_of(blockIdx.x, gridDim.x, order);
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
   const SweepJob job = jobs[j];
-  xmajor_sweep_tile<Q, NT>(job, t - job.first_block, sh);
+  xmajor_sweep_tile<Q, NT, BUFS>(job, t - job.first_block, sh);
 }
 
 __global__ void init_kernel(uint32_t* __restrict__ V, size_t n4, uint32_t start) {
@@ -736,11 +770,22 @@ __global__ void walls_kernel(uint8_t* __restrict__ B, int N, int L) {
 // 512 threads and 32 columns with 512 threads measured slower)
 constexpr int XQ = 32;   // x-major chunk columns
 constexpr int XNT = 256;  // x-major workgroup threads
+constexpr int XBUFS_BUILTIN = 2;  // x-major tile buffers unless a knob says otherwise
 
 }  // namespace
 
 // Steps per wave chosen for a curve length (0 = not set), process-wide.
 static std::atomic<uint8_t> g_section_steps[1025];
+
+int set_knob(int k, int v) {
+  if (k < 0 || k >= kKnobs) return NHP_EINVAL;
+  static const int lo[kKnobs] = {1, 1, 1, 1}, hi[kKnobs] = {8, 16, 2, 2};
+  if (v != 0 && (v < lo[k] || v > hi[k])) return NHP_EINVAL;
+  g_knob[k].store(v, std::memory_order_relaxed);
+  return NHP_OK;
+}
+
+int get_knob(int k) { return (k < 0 || k >= kKnobs) ? -1 : g_knob[k].load(std::memory_order_relaxed); }
 
 bool valid_section(int len, int P) { return (P == 8 || P == 16 || P == 32 || P == 64) && (len + P - 1) / P <= 16; }
 
@@ -797,6 +842,7 @@ int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj) 
   j.n_poses = (uint32_t)N * (uint32_t)N * (uint32_t)L;
   j.ct = d.ct[mu];
   j.tiles_x = tiles_x;
+  j.order = knob(NHP_KNOB_TILE_ORDER, 1);
   int n = 0;
   if (mu == NHP_SF || mu == NHP_SB) {
     j.L = N;
@@ -902,7 +948,10 @@ hipError_t launch_sweep_part(const DevPlan& d, Pass pass, int parts, hipStream_t
     if (e != hipSuccess) return e;
   }
   if (xmaj.blocks && (parts & 2)) {
-    hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT>), dim3(xmajor_grid(xmaj.blocks)), dim3(XNT), 0, s, xmaj);
+    if (knob(NHP_KNOB_XMAJOR_BUFFERS, XBUFS_BUILTIN) == 1)
+      hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 1>), dim3(xmajor_grid(xmaj.blocks)), dim3(XNT), 0, s, xmaj);
+    else
+      hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 2>), dim3(xmajor_grid(xmaj.blocks)), dim3(XNT), 0, s, xmaj);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -915,19 +964,19 @@ hipError_t launch_row_batch_t(const SweepJob* d_jobs, int n_jobs, int total_bloc
   switch (P) {
     case 64:
       hipLaunchKernelGGL((row_sweep_batch_kernel<64, FUSED, GUARD, POW2>), grid, block, 0, s, d_jobs, n_jobs,
-                         total_blocks);
+                         total_blocks, knob(NHP_KNOB_TILE_ORDER, 1));
       break;
     case 32:
       hipLaunchKernelGGL((row_sweep_batch_kernel<32, FUSED, GUARD, POW2>), grid, block, 0, s, d_jobs, n_jobs,
-                         total_blocks);
+                         total_blocks, knob(NHP_KNOB_TILE_ORDER, 1));
       break;
     case 16:
       hipLaunchKernelGGL((row_sweep_batch_kernel<16, FUSED, GUARD, POW2>), grid, block, 0, s, d_jobs, n_jobs,
-                         total_blocks);
+                         total_blocks, knob(NHP_KNOB_TILE_ORDER, 1));
       break;
     case 8:
       hipLaunchKernelGGL((row_sweep_batch_kernel<8, FUSED, GUARD, POW2>), grid, block, 0, s, d_jobs, n_jobs,
-                         total_blocks);
+                         total_blocks, knob(NHP_KNOB_TILE_ORDER, 1));
       break;
     default: return hipErrorInvalidValue;
   }
@@ -945,7 +994,13 @@ hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_bloc
                               bool pow2, bool xmajor, int waves, hipStream_t s) {
   if (n_jobs == 0) return hipSuccess;
   if (xmajor) {
-    hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT>), dim3(total_blocks), dim3(XNT), 0, s, d_jobs, n_jobs);
+    const int order = knob(NHP_KNOB_TILE_ORDER, 1);
+    if (knob(NHP_KNOB_XMAJOR_BUFFERS, XBUFS_BUILTIN) == 1)
+      hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 1>), dim3(total_blocks), dim3(XNT), 0, s, d_jobs, n_jobs,
+                         order);
+    else
+      hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 2>), dim3(total_blocks), dim3(XNT), 0, s, d_jobs, n_jobs,
+                         order);
     return hipGetLastError();
   }
   if (waves < 1 || waves > 16) return hipErrorInvalidValue;

@@ -134,6 +134,14 @@ int nhp_set_section_steps(uint32_t curve_len, uint32_t steps) {
   return ok();
 }
 
+int nhp_set_knob(uint32_t knob, int32_t value) {
+  if (nhp::set_knob((int)knob, (int)value) != NHP_OK)
+    return fail(NHP_EINVAL, "knob %u does not take the value %d", knob, value);
+  return ok();
+}
+
+int32_t nhp_get_knob(uint32_t knob) { return nhp::get_knob((int)knob); }
+
 size_t plan_workspace_bytes(const nhp_params* params) {
   if (check_params(params) != NHP_OK) return 0;
   return layout_of(*params).total;

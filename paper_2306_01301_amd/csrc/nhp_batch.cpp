@@ -13,6 +13,26 @@
 namespace {
 
 constexpr int kSlots = 4;  // job tables in flight (ring), each reused only after its launches finished
+constexpr int kMaxGraphs = 16;  // captured launch sequences kept per batch
+constexpr int kSeen = 64;       // launch sequences remembered (by hash) to capture on their second run
+
+// A launch sequence captured into a graph: its key (the knob values, the job
+// table and the launch list, byte for byte), the device job table its kernels
+// read, and an event recorded after its latest replay.
+struct CachedGraph {
+  std::vector<unsigned char> key;
+  uint64_t hash = 0;
+  hipGraphExec_t exec = nullptr;
+  void* table = nullptr;
+  hipEvent_t last = nullptr;
+  uint64_t used = 0;
+};
+
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t k = 0; k < n; k++) h = (h ^ p[k]) * 1099511628211ull;
+  return h;
+}
 
 struct Slot {
   void* host = nullptr;  // pinned staging buffer
@@ -35,6 +55,11 @@ struct nhp_batch {
   uint32_t capacity = 0;
   Slot slot[kSlots];
   int next = 0;
+  std::vector<CachedGraph> graphs;
+  uint64_t seen[kSeen] = {};
+  int seen_next = 0;
+  uint64_t clock = 0;
+  bool graph_failed = false;  // capture unavailable: launch directly
 };
 
 namespace {
@@ -104,6 +129,11 @@ int batch_create(uint32_t capacity, void* stream, nhp_batch** out) {
 int batch_destroy(nhp_batch* b) {
   if (!b) return nhp::clear_error();
   (void)hipStreamSynchronize(b->stream);
+  for (CachedGraph& g : b->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.table) (void)hipFree(g.table);
+    if (g.last) (void)hipEventDestroy(g.last);
+  }
   for (Slot& s : b->slot) {
     if (s.host) (void)hipHostFree(s.host);
     if (s.dev) (void)hipFree(s.dev);
@@ -274,20 +304,108 @@ static int add_pass(nhp_plan* const* plans, const nhp::Pass* passes, uint32_t n,
   return NHP_OK;
 }
 
-// Uploads the job tables of all passes at once, then launches them in order.
+static hipError_t enqueue_launches(const nhp::SweepJob* d, const std::vector<Launch>& launches, hipStream_t st) {
+  for (const Launch& l : launches) {
+    const hipError_t e = nhp::launch_sweep_batch(d + l.first, l.n_jobs, l.blocks, l.P, l.fused != 0, l.guard != 0,
+                                                 l.pow2 != 0, l.waves == 0, l.waves, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// The launches of a job table captured into a graph over a device copy of the
+// table that the graph owns; nullptr when capture is unavailable.
+static hipGraphExec_t capture_launches(const std::vector<nhp::SweepJob>& table, const std::vector<Launch>& launches,
+                                       void** d_table) {
+  *d_table = nullptr;
+  const size_t bytes = table.size() * sizeof(nhp::SweepJob);
+  if (hipMalloc(d_table, bytes) != hipSuccess) return nullptr;
+  hipStream_t cs = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipMemcpy(*d_table, table.data(), bytes, hipMemcpyHostToDevice) == hipSuccess &&
+            hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    ok = enqueue_launches(reinterpret_cast<const nhp::SweepJob*>(*d_table), launches, cs) == hipSuccess;
+    ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok && g != nullptr;
+  }
+  if (ok) ok = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (!ok) {
+    (void)hipGetLastError();  // clear a sticky capture error
+    if (*d_table) (void)hipFree(*d_table);
+    *d_table = nullptr;
+    return nullptr;
+  }
+  return exec;
+}
+
+// Runs the launches of a job table.  A table (with the same knob values and
+// launch list) seen before in this batch is captured into a graph the second
+// time and replayed from then on (the cycles of a batch_sweep, or a batch of
+// the same plans planned again); otherwise the table is uploaded from a ring
+// slot and the launches go out directly.
 static int run_launches(nhp_batch* b, const std::vector<nhp::SweepJob>& table, const std::vector<Launch>& launches) {
   if (table.empty()) return NHP_OK;
+  std::vector<unsigned char> key(nhp::kKnobs * sizeof(int32_t) + table.size() * sizeof(nhp::SweepJob) +
+                                 launches.size() * sizeof(Launch));
+  unsigned char* kp = key.data();
+  for (int k = 0; k < nhp::kKnobs; k++) {
+    const int32_t v = nhp::get_knob(k);
+    memcpy(kp, &v, sizeof(v));
+    kp += sizeof(v);
+  }
+  memcpy(kp, table.data(), table.size() * sizeof(nhp::SweepJob));
+  kp += table.size() * sizeof(nhp::SweepJob);
+  memcpy(kp, launches.data(), launches.size() * sizeof(Launch));
+  const uint64_t h = fnv1a(key.data(), key.size());
+  for (CachedGraph& g : b->graphs) {
+    if (g.hash != h || g.key != key) continue;
+    HIP_TRY(hipGraphLaunch(g.exec, b->stream), "graph launch");
+    HIP_TRY(hipEventRecord(g.last, b->stream), "hipEventRecord");
+    g.used = ++b->clock;
+    return NHP_OK;
+  }
+  bool again = false;
+  for (uint64_t x : b->seen) again = again || x == h;
+  if (again && !b->graph_failed) {
+    CachedGraph g;
+    g.exec = capture_launches(table, launches, &g.table);
+    if (!g.exec) {
+      b->graph_failed = true;
+    } else {
+      HIP_TRY(hipEventCreateWithFlags(&g.last, hipEventDisableTiming), "hipEventCreate");
+      if ((int)b->graphs.size() >= kMaxGraphs) {
+        // the least recently used graph goes, once its latest replay is done
+        auto victim = std::min_element(b->graphs.begin(), b->graphs.end(),
+                                       [](const CachedGraph& x, const CachedGraph& y) { return x.used < y.used; });
+        HIP_TRY(hipEventSynchronize(victim->last), "hipEventSynchronize");
+        (void)hipGraphExecDestroy(victim->exec);
+        (void)hipFree(victim->table);
+        (void)hipEventDestroy(victim->last);
+        b->graphs.erase(victim);
+      }
+      g.key = std::move(key);
+      g.hash = h;
+      g.used = ++b->clock;
+      b->graphs.push_back(g);
+      CachedGraph& c = b->graphs.back();
+      HIP_TRY(hipGraphLaunch(c.exec, b->stream), "graph launch");
+      HIP_TRY(hipEventRecord(c.last, b->stream), "hipEventRecord");
+      return NHP_OK;
+    }
+  }
+  b->seen[b->seen_next] = h;
+  b->seen_next = (b->seen_next + 1) % kSeen;
   Slot* s;
   int rc = take_slot(b, table.size() * sizeof(nhp::SweepJob), &s);
   if (rc) return rc;
   memcpy(s->host, table.data(), table.size() * sizeof(nhp::SweepJob));
   HIP_TRY(hipMemcpyAsync(s->dev, s->host, table.size() * sizeof(nhp::SweepJob), hipMemcpyHostToDevice, b->stream),
           "job upload");
-  const nhp::SweepJob* d = reinterpret_cast<const nhp::SweepJob*>(s->dev);
-  for (const Launch& l : launches)
-    HIP_TRY(nhp::launch_sweep_batch(d + l.first, l.n_jobs, l.blocks, l.P, l.fused != 0, l.guard != 0, l.pow2 != 0,
-                                    l.waves == 0, l.waves, b->stream),
-            "sweep launch");
+  HIP_TRY(enqueue_launches(reinterpret_cast<const nhp::SweepJob*>(s->dev), launches, b->stream), "sweep launch");
   return finish_slot(b, s);
 }
 
@@ -349,9 +467,39 @@ int batch_sweep(nhp_batch* b, nhp_plan* const* plans, const uint32_t* starts_ijt
   if (!n_cycles) return nhp::set_error(NHP_EINVAL, "n_cycles is NULL");
   rc = batch_init(b, plans, starts_ijt, n);
   if (rc) return rc;
-  std::vector<uint32_t> zero(n, 0), total(n);
-  for (uint32_t k = 0; k < n; k++) total[k] = n_cycles[k] * plans[k]->p.n_schedule;
-  return batch_advance(b, plans, zero.data(), total.data(), n);
+  // One batch_advance per cycle, with the passes sweep_n_turns would run: a
+  // cycle's last sweep shares a pass with the next cycle's first when they
+  // fuse and the plan goes on.  From the third cycle on, the cycles of the
+  // same plans repeat the same launches, which run from a captured graph.
+  uint32_t most = 0;
+  for (uint32_t k = 0; k < n; k++) most = std::max(most, n_cycles[k]);
+  std::vector<uint32_t> done(n, 0), skip(n, 0);
+  std::vector<nhp_plan*> active;
+  std::vector<uint32_t> steps, counts;
+  std::vector<nhp::Pass> v;
+  for (uint32_t c = 0; c < most; c++) {
+    active.clear();
+    steps.clear();
+    counts.clear();
+    for (uint32_t k = 0; k < n; k++) {
+      if (c >= n_cycles[k]) continue;
+      const nhp_plan* p = plans[k];
+      const uint32_t m = p->p.n_schedule;
+      const bool pair_next = c + 1 < n_cycles[k], pairs = nhp::can_fuse(p->d);
+      v.clear();
+      nhp::schedule_passes(p->p.schedule, (int)m, c * (uint64_t)m + skip[k], m - skip[k] + (pair_next ? 1 : 0), pairs,
+                           v);
+      const bool consumed = pair_next && pairs && !v.empty() && v.back().mu2 >= 0;
+      active.push_back(plans[k]);
+      steps.push_back(done[k]);
+      counts.push_back(m - skip[k] + (consumed ? 1 : 0));
+      done[k] += counts.back();
+      skip[k] = consumed ? 1 : 0;
+    }
+    rc = batch_advance(b, active.data(), steps.data(), counts.data(), (uint32_t)active.size());
+    if (rc) return rc;
+  }
+  return nhp::clear_error();
 }
 
 int batch_extract(nhp_batch* b, nhp_plan* const* plans, uint32_t n, const uint32_t* goals_ijt, const uint32_t* radius,

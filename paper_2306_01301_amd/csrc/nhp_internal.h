@@ -80,6 +80,7 @@ struct SweepJob {
   uint32_t n_poses;         // poses of the volume (N N headings)
   int cyclic, dir, mu_forward;
   int tiles_x, blocks, first_block;
+  int order;                // tile order: 1 = tiles sharing row segments on one XCD, 2 = launch order
   int P;                    // steps per wave (row jobs)
   uint32_t ct, lq;          // transition cost; turn edge length
   // Turns only: a second maneuver on the same circles in the opposite
@@ -122,6 +123,11 @@ struct InitJob {
 
 int pick_section(int len);
 int set_section_steps(int len, int P);
+// Launch-shape knobs (enum nhp_knob of nhp.h): set_knob checks the range,
+// get_knob returns the value (0 = built-in) or -1.
+constexpr int kKnobs = 4;
+int set_knob(int knob, int value);
+int get_knob(int knob);
 int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj);
 // Row jobs of one launch share P, fused, guard (= L % P != 0) and their
 // wave count (the workgroup size is 64 waves threads).

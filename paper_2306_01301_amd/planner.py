@@ -83,6 +83,8 @@ SIGNATURES = {
     "plan_get_tables": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "plan_last_error": (ctypes.c_char_p, []),
     "nhp_set_section_steps": (ctypes.c_int, [_u32, _u32]),
+    "nhp_set_knob": (ctypes.c_int, [_u32, _i32]),
+    "nhp_get_knob": (ctypes.c_int32, [_u32]),
     "reach_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(NhpParams), _u32]),
     "reach_create": (ctypes.c_int, [_vp, _u32, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
     "reach_destroy": (ctypes.c_int, [_vp]),
@@ -124,18 +126,41 @@ def lib() -> ctypes.CDLL:
 TUNING_PATH = os.path.join(_HERE, "tuning.json")
 
 
-def apply_tuning(path: str = TUNING_PATH) -> dict:
-    """Hands the measured section sizes (autotune.py) to the library."""
+KNOBS = {"row_wg_per_cu": 0, "xmajor_wg_per_cu": 1, "tile_order": 2, "xmajor_buffers": 3}
+
+
+def load_tuning(path: str = TUNING_PATH) -> dict:
     import json
 
     try:
         with open(path) as f:
-            table = json.load(f).get("section_steps", {})
+            return json.load(f)
     except (OSError, ValueError):
         return {}
+
+
+def apply_tuning_table(table: dict) -> None:
     for length, steps in table.items():
         _lib.nhp_set_section_steps(int(length), int(steps))
+
+
+def apply_tuning(path: str = TUNING_PATH) -> dict:
+    """Hands the measured section sizes and launch knobs (autotune.py) to the library."""
+    doc = load_tuning(path)
+    table = doc.get("section_steps", {})
+    apply_tuning_table(table)
+    for name, value in doc.get("knobs", {}).items():
+        if name in KNOBS:
+            _lib.nhp_set_knob(KNOBS[name], int(value))
     return table
+
+
+def set_knob(knob: int, value: int) -> None:
+    _check(lib().nhp_set_knob(int(knob), int(value)), "nhp_set_knob")
+
+
+def get_knob(knob: int) -> int:
+    return int(lib().nhp_get_knob(int(knob)))
 
 
 def set_section_steps(curve_len: int, steps: int) -> None:

@@ -146,6 +146,37 @@ def traffic(fetch_dir: str, write_dir: str, workload: str, copy_bytes: int, comm
     }
 
 
+def gaps(directory: str) -> dict:
+    """GPU occupancy of a kernel trace after its last fill kernel (the
+    marker the benchmark's batch_64 mode launches): the span from the first
+    to the last kernel, the time no kernel runs, and the same inside the
+    sweep phase (first to last sweep kernel)."""
+    rows = sorted(_rows(directory, "kernel_trace.csv"), key=lambda r: int(r["start_timestamp"]))
+    marks = [i for i, r in enumerate(rows) if "fill" in r["kernel_name"].lower()]
+    run = rows[marks[-1] + 1:] if marks else rows
+
+    def occupancy(rs):
+        iv = sorted((int(r["start_timestamp"]), int(r["end_timestamp"])) for r in rs)
+        busy, gap_list = 0, []
+        cs, ce = iv[0]
+        for s, e in iv[1:]:
+            if s > ce:
+                busy += ce - cs
+                gap_list.append(s - ce)
+                cs, ce = s, e
+            else:
+                ce = max(ce, e)
+        busy += ce - cs
+        span = iv[-1][1] - iv[0][0]
+        gap_list.sort()
+        return {"kernels": len(rs), "span_ms": span / 1e6, "busy_ms": busy / 1e6, "idle_frac": 1 - busy / span,
+                "gaps": len(gap_list), "largest_gaps_ms": [g / 1e6 for g in gap_list[-5:]]}
+
+    sweeps = [k for k, r in enumerate(run) if "sweep" in r["kernel_name"]]
+    inner = run[sweeps[0]:sweeps[-1] + 1] if sweeps else []
+    return {"whole_run": occupancy(run), "sweep_phase": occupancy(inner) if inner else None}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -160,8 +191,13 @@ def main() -> int:
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    g = sub.add_parser("gaps")
+    g.add_argument("dirs", nargs="+")
     a = ap.parse_args()
-    if a.cmd == "stats":
+    if a.cmd == "gaps":
+        json.dump({d: gaps(d) for d in a.dirs}, sys.stdout, indent=1)
+        sys.stdout.write("\n")
+    elif a.cmd == "stats":
         sys.stdout.write(stats_table(a.dir, a.title, a.command))
     else:
         json.dump(traffic(a.fetch, a.write, a.workload, a.copy_bytes, (a.command_fetch, a.command_write)),

@@ -156,13 +156,18 @@ class _Live:
         return (self.total - self.done) * self.scene.n_poses
 
 
-# Scheduling of a tick (measured on the MI355X; see tick_plan).
+# Scheduling of a tick (see tick_plan); the autotuner's measured choice in
+# tuning.json replaces the first three.
 FILL_POSES = 64 << 20    # poses a tick's passes cover together before it stops adding plans
 TICK_POSES = 1 << 30     # pose updates each selected plan gets per tick (at least one pass)
+ADMIT_PER_TICK = 4       # requests per hand-over to the admission thread
 AGING = 1.0              # seconds of expected work a second of waiting is worth
 UPDATE_RATE = 6.0e11     # pose updates per second of the sweep kernels, for the expected-work estimate
 MAX_QUEUED_TICKS = 2     # ticks enqueued ahead of the GPU
-ADMIT_PER_TICK = 4       # requests per hand-over to the admission thread
+_tuned = P.load_tuning().get("server", {})
+FILL_POSES = int(_tuned.get("fill_poses", FILL_POSES))
+TICK_POSES = int(_tuned.get("tick_poses", TICK_POSES))
+ADMIT_PER_TICK = int(_tuned.get("admit_per_tick", ADMIT_PER_TICK))
 
 
 def tick_plan(live: Sequence[_Live], now: float, fill_poses: int = FILL_POSES, tick_poses: int = TICK_POSES,

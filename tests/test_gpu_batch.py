@@ -199,3 +199,41 @@ def test_batch_of_config4_shapes_matches_oracle():
     batch.close()
     for p in planners:
         p.close()
+
+
+def test_batch_cycle_graph_replays_match_oracle():
+    """batch_sweep replays repeated cycles from captured graphs (within a
+    call from the third cycle on, and whole calls on the same plans): the
+    same plans swept again with new starts, with other GPU work and
+    synchronisations between the calls, match the oracle every time."""
+    rng = np.random.default_rng(4343)
+    scs = [scenes.random_small(201, n=64, nt=64, R=6.0, n_cycles=6),
+           scenes.random_small(202, n=48, nt=40, R=4.0, n_cycles=5),
+           scenes.random_instance(rng, sides=(128,), thetas=(128,), n_range=(6, 6))]
+    planners = [P.planner_for(sc) for sc in scs]
+    batch = P.Batch(len(scs))
+    batch.render(planners, [_dev(sc.image) for sc in scs], [sc.vehicle for sc in scs])
+    for rep in range(4):
+        starts = []
+        for sc in scs:  # a new collision-free start per repetition (the first: the scene's own)
+            prob = problem_of(sc)
+            B = oracle.render(prob, sc.image, *sc.vehicle)
+            if rep == 0:
+                starts.append(tuple(sc.start))
+                continue
+            free = np.argwhere(B != 255)
+            t, j, i = free[rng.integers(len(free))]
+            starts.append((int(i), int(j), int(t)))
+        print("batch graph replay %d starts %s" % (rep, starts), flush=True)
+        batch.sweep(planners, starts, [sc.n_cycles for sc in scs])
+        torch.zeros(1 << 20, device="cuda").add_(1.0)  # other work between the calls
+        torch.cuda.synchronize()
+        for k, sc in enumerate(scs):
+            prob = problem_of(sc)
+            B = oracle.render(prob, sc.image, *sc.vehicle)
+            V = oracle.init(prob, B, starts[k])
+            oracle.cycles(prob, B, V, sc.n_cycles)
+            assert np.array_equal(planners[k].value_numpy(), V), (rep, k)
+    batch.close()
+    for p in planners:
+        p.close()
