@@ -496,8 +496,12 @@ struct XShared {
   static constexpr int NW = NT / 64;    // waves
   static constexpr int PITCH = Q + 1;   // odd pitch: lanes reading one column of 64 lines hit 64 banks
   static constexpr int SLOTS = (LINES + 1) * PITCH;  // 64 lines and the spare row
+  // codes: rows of Q bytes padded to an odd number of words, so the byte
+  // reads of one column of 64 lines also fall in distinct banks
+  static constexpr int PITCH_B = 4 * (Q / 4 + ((Q / 4) % 2 == 0 ? 1 : 0));
+  static constexpr int SLOTS_B = (LINES + 1) * PITCH_B;
   uint32_t tV[BUFS][SLOTS];
-  uint8_t tB[BUFS][SLOTS];
+  uint8_t tB[BUFS][SLOTS_B];
   uint32_t aggD[NW][64];
   uint32_t aggC[NW][64];
   uint32_t wlut[256];
@@ -507,7 +511,8 @@ struct XShared {
 template <int Q, int NT, int BUFS>
 __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, XShared<Q, NT, BUFS>& sh) {
   using X = XShared<Q, NT, BUFS>;
-  constexpr int LINES = X::LINES, PITCH = X::PITCH, NW = X::NW;
+  constexpr int LINES = X::LINES, PITCH = X::PITCH, PITCH_B = X::PITCH_B, NW = X::NW;
+  static_assert((PITCH_B / 4) % 2 == 1 && PITCH_B % 4 == 0 && PITCH_B >= Q, "odd word pitch for the codes");
   constexpr int SUB = Q / NW;   // columns per wave
   constexpr int ROWS = NT / Q;  // band rows per load round
   constexpr int ITER = (LINES + Q - 1 + ROWS - 1) / ROWS;
@@ -535,6 +540,7 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
   const int r0 = tid / Q;  // first band row of this thread; rows r0 + it * ROWS
   const int t_lim = (N - x0) < LINES ? (N - x0) : LINES;  // lines of this tile inside the grid
   const uint32_t spare = LINES * PITCH + kk;               // LDS slot for cells no line owns
+  const uint32_t spare_b = LINES * PITCH_B + kk;
   constexpr uint32_t kNoRecord = 0xFFFFFFFFu;
 
   uint32_t carry = kInf;  // value carried along line x0 + lane into the chunk
@@ -580,9 +586,9 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
       asm volatile("" : "+v"(t));
 #pragma unroll
       for (int it = 0; it < ITER; it++) {
-        const uint32_t slot = (uint32_t)t < tl ? (uint32_t)(t * PITCH + kk) : spare;
-        tV[slot] = lv[it];
-        tB[slot] = (uint8_t)lc[it];
+        const bool own = (uint32_t)t < tl;
+        tV[own ? (uint32_t)(t * PITCH + kk) : spare] = lv[it];
+        tB[own ? (uint32_t)(t * PITCH_B + kk) : spare_b] = (uint8_t)lc[it];
         t += ROWS;
       }
     }
@@ -590,12 +596,13 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
 
     // scan: wave w takes columns [w SUB, (w+1) SUB) of the chunk for all 64 lines
     const int line_slot = lane * PITCH + wave * SUB;
+    const int line_slot_b = lane * PITCH_B + wave * SUB;
     uint32_t u[SUB], w[SUB];
 #pragma unroll
     for (int q = 0; q < SUB; q++) {
       const bool ok = wave * SUB + q < nq;  // uniform
       u[q] = ok ? tV[line_slot + q] : kInf;
-      w[q] = ok ? sh.wlut[tB[line_slot + q]] : 0u;
+      w[q] = ok ? sh.wlut[tB[line_slot_b + q]] : 0u;
     }
     uint32_t D = 0, C = kInf;
 #pragma unroll
