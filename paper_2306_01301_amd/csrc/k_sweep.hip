@@ -84,6 +84,8 @@ __device__ __forceinline__ uint32_t row_cell(uint32_t g, uint32_t x, uint32_t sh
 
 constexpr int kBufferWord3 = 0x00020000;  // descriptor word 3 for untyped access on gfx9-family GPUs
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 struct RowBuffers {
   __amdgpu_buffer_rsrc_t V, B;
 };
@@ -508,15 +510,18 @@ struct XShared {
   int16_t skew[1024];  // B(c, T) of this plane
 };
 
-template <int Q, int NT, int BUFS>
+template <int Q, int NT, int BUFS, bool WIDE>
 __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, XShared<Q, NT, BUFS>& sh) {
   using X = XShared<Q, NT, BUFS>;
   constexpr int LINES = X::LINES, PITCH = X::PITCH, PITCH_B = X::PITCH_B, NW = X::NW;
   static_assert((PITCH_B / 4) % 2 == 1 && PITCH_B % 4 == 0 && PITCH_B >= Q, "odd word pitch for the codes");
   constexpr int SUB = Q / NW;   // columns per wave
-  constexpr int ROWS = NT / Q;  // band rows per load round
+  constexpr int ROWS = NT / Q;  // band rows per load round (a column per thread)
   constexpr int ITER = (LINES + Q - 1 + ROWS - 1) / ROWS;
-  static_assert(NT % Q == 0 && Q % NW == 0, "Q must divide the thread count and split over the waves");
+  constexpr int GW = Q / 4;       // WIDE: groups of 4 columns per chunk
+  constexpr int ROWS4 = NT / GW;  // WIDE: band rows per load round (4 columns per thread)
+  constexpr int ITER4 = (LINES + Q - 1 + ROWS4 - 1) / ROWS4;
+  static_assert(NT % Q == 0 && Q % NW == 0 && Q % 4 == 0, "Q must divide the thread count and split over the waves");
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -529,6 +534,11 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
       __builtin_amdgcn_make_buffer_rsrc(a.V + (size_t)T * NN, (short)4, (int)NN, kBufferWord3);
   const __amdgpu_buffer_rsrc_t bB =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.B) + (size_t)T * NN, (short)1, (int)NN, kBufferWord3);
+  // the same planes addressed by byte offset (WIDE loads)
+  const __amdgpu_buffer_rsrc_t rV =
+      __builtin_amdgcn_make_buffer_rsrc(a.V + (size_t)T * NN, (short)0, (int)(NN * 4u), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rB =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.B) + (size_t)T * NN, (short)0, (int)NN, kBufferWord3);
   const uint32_t Lq = a.edge_len[T];
   for (int c = tid; c < 256; c += NT) sh.wlut[c] = weight((uint32_t)c, 256u * Lq + 128u, 4u * Lq);
   const int dir = (a.fwd[T] > 0) == (a.mu_forward != 0);
@@ -538,10 +548,13 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
   const int16_t* sk = sh.skew;
   const int kk = tid % Q;  // column of this thread in the load/store phases
   const int r0 = tid / Q;  // first band row of this thread; rows r0 + it * ROWS
+  const int gw = tid % GW;   // WIDE: column group of this thread
+  const int r0w = tid / GW;  // WIDE: first band row of this thread; rows r0w + it * ROWS4
   const int t_lim = (N - x0) < LINES ? (N - x0) : LINES;  // lines of this tile inside the grid
   const uint32_t spare = LINES * PITCH + kk;               // LDS slot for cells no line owns
   const uint32_t spare_b = LINES * PITCH_B + kk;
   constexpr uint32_t kNoRecord = 0xFFFFFFFFu;
+  constexpr uint32_t kNoOffset = 0xFFFFFFF0u;  // past the end of either plane: loads nothing
 
   uint32_t carry = kInf;  // value carried along line x0 + lane into the chunk
   int buf = 0;
@@ -561,26 +574,64 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
     const int my_c = dir ? (k0 + kk) : (N - 1 - (k0 + kk));
     const int my_b = sk[col_ok ? my_c : c_first];
     const uint32_t tl = col_ok ? (uint32_t)t_lim : 0u;
-
-    // load the band: band row r holds line t = r + bmin - B(c) of column c
     int row = band0 + r0;
     row -= (row >= N) ? N : 0;
     const uint32_t rel0 = (uint32_t)row * (uint32_t)N + (uint32_t)(col_ok ? my_c : 0);
     const int t0 = r0 + bmin - my_b;
-    uint32_t lv[ITER], lc[ITER];
-    {
-      uint32_t rel = rel0;
-      int t = t0;
+
+    // load the band: band row r holds line t = r + bmin - B(c) of column c
+    if (WIDE) {
+      // 4 adjacent columns per thread (16 bytes of values, 4 codes) in rows
+      // r0w, r0w + ROWS4, ...: in memory order they are columns cw .. cw + 3,
+      // and memory word m is chunk column 4 gw + (dir ? m : 3 - m).  A group
+      // that no line of the tile owns in a row loads nothing; a partly owned
+      // group loads all four (the other cells are the neighbouring tile's and
+      // are neither kept nor stored).  Needs ROWS4 <= N (one wrap per step).
+      const bool grp_ok = 4 * gw < nq;
+      const int cw = grp_ok ? (dir ? (k0 + 4 * gw) : (N - 4 - k0 - 4 * gw)) : 0;
+      const uint32_t tlw = grp_ok ? (uint32_t)t_lim : 0u;
+      int rw = band0 + r0w;
+      rw -= (rw >= N) ? N : 0;
+      uint32_t base = (uint32_t)rw * (uint32_t)N + (uint32_t)cw;
+      int tw[4];
 #pragma unroll
-      for (int it = 0; it < ITER; it++) {
-        const uint32_t idx = (uint32_t)t < tl ? rel : kNoRecord;
-        lv[it] = buffer_load_u32(bV, idx, 0, 0, 0);
-        lc[it] = buffer_load_u8(bB, idx, 0, 0, 0);
-        t += ROWS;
-        rel = wrap_col(rel + (uint32_t)(ROWS * N), (int)NN);  // ROWS rows down, wrapping around the plane
+      for (int m = 0; m < 4; m++) tw[m] = r0w + bmin - sk[cw + m];
+      u32x4 lv4[ITER4];
+      uint32_t lc4[ITER4];
+#pragma unroll
+      for (int it = 0; it < ITER4; it++) {
+        bool any = false;
+#pragma unroll
+        for (int m = 0; m < 4; m++) any = any || (uint32_t)(tw[m] + it * ROWS4) < tlw;
+        lv4[it] = __builtin_amdgcn_raw_buffer_load_b128(rV, any ? base * 4u : kNoOffset, 0, 0);
+        lc4[it] = __builtin_amdgcn_raw_buffer_load_b32(rB, any ? base : kNoOffset, 0, 0);
+        base = wrap_col(base + (uint32_t)(ROWS4 * N), (int)NN);  // ROWS4 rows down, wrapping around the plane
       }
-    }
-    {
+#pragma unroll
+      for (int it = 0; it < ITER4; it++) {
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+          const int t = tw[m] + it * ROWS4;
+          const int kj = 4 * gw + (dir ? m : 3 - m);
+          const bool own = (uint32_t)t < tlw;
+          tV[own ? (uint32_t)(t * PITCH + kj) : (uint32_t)(LINES * PITCH + kj)] = lv4[it][m];
+          tB[own ? (uint32_t)(t * PITCH_B + kj) : (uint32_t)(LINES * PITCH_B + kj)] = (uint8_t)(lc4[it] >> (8 * m));
+        }
+      }
+    } else {
+      uint32_t lv[ITER], lc[ITER];
+      {
+        uint32_t rel = rel0;
+        int t = t0;
+#pragma unroll
+        for (int it = 0; it < ITER; it++) {
+          const uint32_t idx = (uint32_t)t < tl ? rel : kNoRecord;
+          lv[it] = buffer_load_u32(bV, idx, 0, 0, 0);
+          lc[it] = buffer_load_u8(bB, idx, 0, 0, 0);
+          t += ROWS;
+          rel = wrap_col(rel + (uint32_t)(ROWS * N), (int)NN);  // ROWS rows down, wrapping around the plane
+        }
+      }
       // the slots are recomputed rather than kept from the loads (registers)
       int t = t0;
       asm volatile("" : "+v"(t));
@@ -626,7 +677,38 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
     __syncthreads();
 
     // store the band back (cells no line owns have no record: dropped)
-    {
+    if (WIDE) {
+      // the same 4-column groups as the loads: a group the tile owns whole
+      // goes back in one 16-byte store, a partly owned one cell by cell
+      const bool grp_ok = 4 * gw < nq;
+      const int cw = grp_ok ? (dir ? (k0 + 4 * gw) : (N - 4 - k0 - 4 * gw)) : 0;
+      const uint32_t tlw = grp_ok ? (uint32_t)t_lim : 0u;
+      int rw = band0 + r0w;
+      rw -= (rw >= N) ? N : 0;
+      uint32_t base = (uint32_t)rw * (uint32_t)N + (uint32_t)cw;
+      int tw[4];
+#pragma unroll
+      for (int m = 0; m < 4; m++) tw[m] = r0w + bmin - sk[cw + m];
+#pragma unroll
+      for (int it = 0; it < ITER4; it++) {
+        u32x4 val;
+        bool own[4], all = true;
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+          const int t = tw[m] + it * ROWS4;
+          const int kj = 4 * gw + (dir ? m : 3 - m);
+          own[m] = (uint32_t)t < tlw;
+          all = all && own[m];
+          val[m] = tV[own[m] ? (uint32_t)(t * PITCH + kj) : (uint32_t)(LINES * PITCH + kj)];
+        }
+        __builtin_amdgcn_raw_buffer_store_b128(val, rV, all ? base * 4u : kNoOffset, 0, 0);
+        if (!all) {
+#pragma unroll
+          for (int m = 0; m < 4; m++) buffer_store_u32(val[m], bV, own[m] ? base + (uint32_t)m : kNoRecord, 0, 0, 0);
+        }
+        base = wrap_col(base + (uint32_t)(ROWS4 * N), (int)NN);
+      }
+    } else {
       uint32_t rel = rel0;
       int t = t0;
       asm volatile("" : "+v"(t), "+v"(rel));
@@ -704,11 +786,13 @@ int row_grid(int blocks, int waves, int P) {
 // x-major workgroups stay resident too.  A tile's stores read only the LDS
 // band, and the next tile writes its band after the barrier that follows its
 // weight and skew tables, so a wave still storing never sees it overwritten.
-template <int Q, int NT, int BUFS>
-__global__ __launch_bounds__(NT) void xmajor_sweep_kernel(SweepJob job) {
+// (six workgroups of NT threads per CU fit the LDS: ask the register
+// allocator for the occupancy that allows)
+template <int Q, int NT, int BUFS, bool WIDE>
+__global__ __launch_bounds__(NT, 6) void xmajor_sweep_kernel(SweepJob job) {
   __shared__ XShared<Q, NT, BUFS> sh;
   for (int b = blockIdx.x; b < job.blocks; b += gridDim.x)
-    xmajor_sweep_tile<Q, NT, BUFS>(job, tile_of(b, job.blocks, job.order), sh);
+    xmajor_sweep_tile<Q, NT, BUFS, WIDE>(job, tile_of(b, job.blocks, job.order), sh);
 }
 
 // Resident x-major workgroups: 8 per CU (about what fits at once).
@@ -717,14 +801,14 @@ int xmajor_grid(int blocks) {
   return blocks < cap ? blocks : cap;
 }
 
-template <int Q, int NT, int BUFS>
-__global__ __launch_bounds__(NT) void xmajor_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs,
+template <int Q, int NT, int BUFS, bool WIDE>
+__global__ __launch_bounds__(NT, 6) void xmajor_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs,
                                                                  int order) {
   __shared__ XShared<Q, NT, BUFS> sh;
   const int t = tile_of(blockIdx.x, gridDim.x, order);
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
   const SweepJob job = jobs[j];
-  xmajor_sweep_tile<Q, NT, BUFS>(job, t - job.first_block, sh);
+  xmajor_sweep_tile<Q, NT, BUFS, WIDE>(job, t - job.first_block, sh);
 }
 
 __global__ void init_kernel(uint32_t* __restrict__ V, size_t n4, uint32_t start) {
@@ -778,6 +862,14 @@ __global__ void walls_kernel(uint8_t* __restrict__ B, int N, int L) {
 constexpr int XQ = 32;   // x-major chunk columns
 constexpr int XNT = 256;  // x-major workgroup threads
 constexpr int XBUFS_BUILTIN = 2;  // x-major tile buffers unless a knob says otherwise
+
+}  // namespace
+
+// Whether the x-major kernel takes 4-column loads for grids of side N: a load
+// round covers XNT / (XQ / 4) band rows, which must not exceed N (one wrap).
+bool xmajor_wide(int N) { return N >= XNT / (XQ / 4); }
+
+namespace {
 
 }  // namespace
 
@@ -955,10 +1047,12 @@ hipError_t launch_sweep_part(const DevPlan& d, Pass pass, int parts, hipStream_t
     if (e != hipSuccess) return e;
   }
   if (xmaj.blocks && (parts & 2)) {
-    if (knob(NHP_KNOB_XMAJOR_BUFFERS, XBUFS_BUILTIN) == 1)
-      hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 1>), dim3(xmajor_grid(xmaj.blocks)), dim3(XNT), 0, s, xmaj);
-    else
-      hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 2>), dim3(xmajor_grid(xmaj.blocks)), dim3(XNT), 0, s, xmaj);
+    const dim3 grid(xmajor_grid(xmaj.blocks)), block(XNT);
+    const bool one = knob(NHP_KNOB_XMAJOR_BUFFERS, XBUFS_BUILTIN) == 1, wide = xmajor_wide(xmaj.N);
+    if (one && wide) hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 1, true>), grid, block, 0, s, xmaj);
+    if (one && !wide) hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 1, false>), grid, block, 0, s, xmaj);
+    if (!one && wide) hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 2, true>), grid, block, 0, s, xmaj);
+    if (!one && !wide) hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 2, false>), grid, block, 0, s, xmaj);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -1002,12 +1096,13 @@ hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_bloc
   if (n_jobs == 0) return hipSuccess;
   if (xmajor) {
     const int order = knob(NHP_KNOB_TILE_ORDER, 1);
-    if (knob(NHP_KNOB_XMAJOR_BUFFERS, XBUFS_BUILTIN) == 1)
-      hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 1>), dim3(total_blocks), dim3(XNT), 0, s, d_jobs, n_jobs,
-                         order);
-    else
-      hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 2>), dim3(total_blocks), dim3(XNT), 0, s, d_jobs, n_jobs,
-                         order);
+    const bool one = knob(NHP_KNOB_XMAJOR_BUFFERS, XBUFS_BUILTIN) == 1;
+    const dim3 grid(total_blocks), block(XNT);
+    // (for x-major launches `pow2` says every job's grid takes 4-column loads)
+    if (one && pow2) hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 1, true>), grid, block, 0, s, d_jobs, n_jobs, order);
+    if (one && !pow2) hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 1, false>), grid, block, 0, s, d_jobs, n_jobs, order);
+    if (!one && pow2) hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 2, true>), grid, block, 0, s, d_jobs, n_jobs, order);
+    if (!one && !pow2) hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 2, false>), grid, block, 0, s, d_jobs, n_jobs, order);
     return hipGetLastError();
   }
   if (waves < 1 || waves > 16) return hipErrorInvalidValue;

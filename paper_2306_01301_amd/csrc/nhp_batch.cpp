@@ -290,7 +290,7 @@ static int add_pass(nhp_plan* const* plans, const nhp::Pass* passes, uint32_t n,
       group_of(row.P, row.fused, row.L % row.P != 0, (row.N & (row.N - 1)) == 0, (row.L + row.P - 1) / row.P)
           .jobs.push_back(row);
     }
-    if (xm.blocks) group_of(0, 0, 0, 0, 0).jobs.push_back(xm);
+    if (xm.blocks) group_of(0, 0, 0, nhp::xmajor_wide(xm.N) ? 1 : 0, 0).jobs.push_back(xm);
   }
   for (Group& g : groups) {
     Launch l{table.size(), (int)g.jobs.size(), 0, g.P, g.fused, g.guard, g.pow2, g.waves};

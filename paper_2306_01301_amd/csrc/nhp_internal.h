@@ -129,8 +129,12 @@ constexpr int kKnobs = 4;
 int set_knob(int knob, int value);
 int get_knob(int knob);
 int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj);
+// Whether x-major jobs of grid side N take the 4-column-load kernel (batched
+// x-major launches group their jobs by it and pass it as `pow2`).
+bool xmajor_wide(int N);
 // Row jobs of one launch share P, fused, guard (= L % P != 0) and their
-// wave count (the workgroup size is 64 waves threads).
+// wave count (the workgroup size is 64 waves threads); x-major jobs of one
+// launch share xmajor_wide(N), passed as pow2.
 hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_blocks, int P, bool fused, bool guard,
                               bool pow2, bool xmajor, int waves, hipStream_t s);
 hipError_t launch_init_batch(const InitJob* d_jobs, int n_jobs, size_t max_n4, hipStream_t s);
