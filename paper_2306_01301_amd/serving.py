@@ -356,9 +356,19 @@ class Server:
                     for l in done:
                         self.s_extract.wait_event(l.finish_event)
                         l.planner.set_stream(self.s_extract)  # its own work (digest, destroy) waits on this stream
-                    paths = self.b_extract.extract([l.planner for l in done], [l.scene.goal for l in done],
-                                                   [l.scene.goal_radius for l in done],
-                                                   [l.scene.w_xy for l in done], [l.scene.w_t for l in done])
+                    if len(done) == 1:
+                        # one plan: extract_path, whose back-tracking spreads each step over one
+                        # workgroup per scheduled maneuver (a batch gives each plan one workgroup)
+                        l = done[0]
+                        try:
+                            paths = [l.planner.extract(l.scene.goal, l.scene.goal_radius, l.scene.w_xy,
+                                                       l.scene.w_t, cap=512)]
+                        except P.NhpError as e:
+                            paths = [e.rc]
+                    else:
+                        paths = self.b_extract.extract([l.planner for l in done], [l.scene.goal for l in done],
+                                                       [l.scene.goal_radius for l in done],
+                                                       [l.scene.w_xy for l in done], [l.scene.w_t for l in done])
                     t = clock() - t0
                     for l, path in zip(done, paths):
                         r = results[l.k]
