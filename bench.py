@@ -183,34 +183,37 @@ def batch_comparison() -> dict:
 def bench_serving(args) -> int:
     """Continuous batching under Poisson arrivals of mixed requests (sides up
     to 1024, headings up to 512, N up to 20), admitted by HBM footprint."""
-    import torch
+    from paper_2306_01301_amd import scenes, serving
 
-    from paper_2306_01301_amd import scenes, serving, sizing
-
-    reqs = scenes.serving_requests(count=args.requests)
-    free, total = torch.cuda.mem_get_info()
-    budget = int(0.8 * free)
+    pool = scenes.serving_requests(count=args.requests)
+    budget = int(args.serve_budget_gib * (1 << 30))
     rates = [float(r) for r in args.rates.split(",") if r]
     warm = serving.Server(budget, max_live=64)
-    warm.run(reqs[:4], [0.0] * 4)
+    warm.run(pool[:4], [0.0] * 4)
     warm.close()
     per_rate = []
     for rate in rates:
+        # a window of `seconds` of arrivals (at most --max-requests), cycling the pool of distinct requests
+        count = len(pool) if args.seconds <= 0 else min(args.max_requests, max(len(pool), int(args.seconds * rate)))
+        reqs = [pool[k % len(pool)] for k in range(count)]
         arr = scenes.poisson_arrivals(1306 + int(rate), rate, len(reqs))
         srv = serving.Server(budget, max_live=64)
         res = srv.run(reqs, arr)
         srv.close()
         s = serving.latency_summary(res)
         s["rate"] = rate
+        s["requests"] = len(reqs)
+        s["peak_admitted_bytes"] = srv.peak_held
+        s["admission_waits"] = srv.admission_waits
+        print(json.dumps({"rate": rate, "server": s}), file=sys.stderr, flush=True)
         s["one_plan_at_a_time"] = serving.latency_summary(serving.run_fifo(reqs, arr))
         per_rate.append(s)
-        print(json.dumps({"rate": rate, **{k: v for k, v in s.items() if k != "rate"}}), file=sys.stderr, flush=True)
-    updates = sum(sizing.pose_updates(s.nx, s.nt, s.n_cycles, len(s.schedule)) for s in reqs)
+        print(json.dumps({"rate": rate, "fifo": s["one_plan_at_a_time"]}), file=sys.stderr, flush=True)
     best = max(per_rate, key=lambda s: s["plans_per_s"] or 0)
     out = {"metric": METRIC, "value": best["plans_per_s"], "unit": "plans/s", "n_gpus": 1, "steps": len(rates),
            "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "u32", "data": "synthetic",
-           "config": {"workload": "serving_requests", "requests": len(reqs), "pose_updates": updates,
+           "config": {"workload": "serving_requests", "distinct_requests": len(pool), "seconds_per_rate": args.seconds,
                       "hbm_budget_bytes": budget, "admission": "25 B/pose (3 vertices x 2 gears x 4 B + 1 B)"},
            "serving": per_rate}
     print(json.dumps(out), flush=True)
@@ -325,6 +328,42 @@ def bench_batch_modes(args) -> int:
     return 0
 
 
+def other_workloads(reps: int = 20) -> dict:
+    """The paper-shaped small workloads through the plain entry points
+    (render_cspace, sweep_n_turns, extract_path) on a planner made once:
+    median time per whole plan and the sweep throughput."""
+    import torch
+
+    from paper_2306_01301_amd import planner, scenes, sizing
+
+    out = {}
+    for name in ("parking_256", "plain_64"):
+        sc = scenes.WORKLOADS[name]()
+        p = planner.planner_for(sc)
+        image = torch.from_numpy(np.ascontiguousarray(sc.image)).cuda()
+
+        def plan():
+            p.render(image, sc.vehicle)
+            p.sweep(sc.start, sc.n_cycles)
+            return p.extract(sc.goal, sc.goal_radius, sc.w_xy, sc.w_t)
+
+        for _ in range(3):
+            plan()
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            path = plan()  # extract synchronises
+            times.append(time.perf_counter() - t0)
+        ms = 1000.0 * float(np.median(times))
+        updates = sizing.pose_updates(sc.nx, sc.nt, sc.n_cycles, len(sc.schedule))
+        out[name] = {"grid": [sc.nx, sc.nx, sc.nt], "n_cycles": sc.n_cycles, "ms_per_plan": ms,
+                     "plans_per_s": 1000.0 / ms, "pose_updates_per_s": updates / (ms * 1e-3),
+                     "plan_maneuvers": len(path.steps), "reps": reps}
+        p.close()
+    return out
+
+
 def serving_block(rates, count: int, budget: int) -> dict:
     """Continuous batching under Poisson arrivals of the mixed serving
     requests, against the same arrivals served one plan at a time, per
@@ -373,7 +412,10 @@ def main() -> int:
     ap.add_argument("--mode", default="batched", help="batch_64 workload: batched, continuous or single")
     ap.add_argument("--rates", default="10,20,50,100,200,500",
                     help="serving workload: Poisson arrival rates in plans/s")
-    ap.add_argument("--requests", type=int, default=48, help="serving workload: requests per rate")
+    ap.add_argument("--requests", type=int, default=300, help="serving workload: distinct requests (the pool)")
+    ap.add_argument("--seconds", type=float, default=0.0,
+                    help="serving workload: seconds of arrivals per rate, cycling the pool (0: the pool once)")
+    ap.add_argument("--max-requests", type=int, default=1200, help="serving workload: cap on requests per rate")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -555,6 +597,7 @@ def main() -> int:
                                      / 1e9 / HBM_PEAK_GBS}},
     }
     p.close()
+    out["other_workloads"] = other_workloads()
     if not args.skip_batch:
         out["latency_ms"]["batch_64"] = batch_comparison()
     if not args.skip_serving:
