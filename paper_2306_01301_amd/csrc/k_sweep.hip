@@ -510,7 +510,7 @@ struct XShared {
   int16_t skew[1024];  // B(c, T) of this plane
 };
 
-template <int Q, int NT, int BUFS, bool WIDE>
+template <int Q, int NT, int BUFS>
 __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, XShared<Q, NT, BUFS>& sh) {
   using X = XShared<Q, NT, BUFS>;
   constexpr int LINES = X::LINES, PITCH = X::PITCH, PITCH_B = X::PITCH_B, NW = X::NW;
@@ -518,9 +518,6 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
   constexpr int SUB = Q / NW;   // columns per wave
   constexpr int ROWS = NT / Q;  // band rows per load round (a column per thread)
   constexpr int ITER = (LINES + Q - 1 + ROWS - 1) / ROWS;
-  constexpr int GW = Q / 4;       // WIDE: groups of 4 columns per chunk
-  constexpr int ROWS4 = NT / GW;  // WIDE: band rows per load round (4 columns per thread)
-  constexpr int ITER4 = (LINES + Q - 1 + ROWS4 - 1) / ROWS4;
   static_assert(NT % Q == 0 && Q % NW == 0 && Q % 4 == 0, "Q must divide the thread count and split over the waves");
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -534,11 +531,6 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
       __builtin_amdgcn_make_buffer_rsrc(a.V + (size_t)T * NN, (short)4, (int)NN, kBufferWord3);
   const __amdgpu_buffer_rsrc_t bB =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.B) + (size_t)T * NN, (short)1, (int)NN, kBufferWord3);
-  // the same planes addressed by byte offset (WIDE loads)
-  const __amdgpu_buffer_rsrc_t rV =
-      __builtin_amdgcn_make_buffer_rsrc(a.V + (size_t)T * NN, (short)0, (int)(NN * 4u), kBufferWord3);
-  const __amdgpu_buffer_rsrc_t rB =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.B) + (size_t)T * NN, (short)0, (int)NN, kBufferWord3);
   const uint32_t Lq = a.edge_len[T];
   for (int c = tid; c < 256; c += NT) sh.wlut[c] = weight((uint32_t)c, 256u * Lq + 128u, 4u * Lq);
   const int dir = (a.fwd[T] > 0) == (a.mu_forward != 0);
@@ -548,13 +540,10 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
   const int16_t* sk = sh.skew;
   const int kk = tid % Q;  // column of this thread in the load/store phases
   const int r0 = tid / Q;  // first band row of this thread; rows r0 + it * ROWS
-  const int gw = tid % GW;   // WIDE: column group of this thread
-  const int r0w = tid / GW;  // WIDE: first band row of this thread; rows r0w + it * ROWS4
   const int t_lim = (N - x0) < LINES ? (N - x0) : LINES;  // lines of this tile inside the grid
   const uint32_t spare = LINES * PITCH + kk;               // LDS slot for cells no line owns
   const uint32_t spare_b = LINES * PITCH_B + kk;
   constexpr uint32_t kNoRecord = 0xFFFFFFFFu;
-  constexpr uint32_t kNoOffset = 0xFFFFFFF0u;  // past the end of either plane: loads nothing
 
   uint32_t carry = kInf;  // value carried along line x0 + lane into the chunk
   int buf = 0;
@@ -580,58 +569,20 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
     const int t0 = r0 + bmin - my_b;
 
     // load the band: band row r holds line t = r + bmin - B(c) of column c
-    if (WIDE) {
-      // 4 adjacent columns per thread (16 bytes of values, 4 codes) in rows
-      // r0w, r0w + ROWS4, ...: in memory order they are columns cw .. cw + 3,
-      // and memory word m is chunk column 4 gw + (dir ? m : 3 - m).  A group
-      // that no line of the tile owns in a row loads nothing; a partly owned
-      // group loads all four (the other cells are the neighbouring tile's and
-      // are neither kept nor stored).  Needs ROWS4 <= N (one wrap per step).
-      const bool grp_ok = 4 * gw < nq;
-      const int cw = grp_ok ? (dir ? (k0 + 4 * gw) : (N - 4 - k0 - 4 * gw)) : 0;
-      const uint32_t tlw = grp_ok ? (uint32_t)t_lim : 0u;
-      int rw = band0 + r0w;
-      rw -= (rw >= N) ? N : 0;
-      uint32_t base = (uint32_t)rw * (uint32_t)N + (uint32_t)cw;
-      int tw[4];
+    uint32_t lv[ITER], lc[ITER];
+    {
+      uint32_t rel = rel0;
+      int t = t0;
 #pragma unroll
-      for (int m = 0; m < 4; m++) tw[m] = r0w + bmin - sk[cw + m];
-      u32x4 lv4[ITER4];
-      uint32_t lc4[ITER4];
-#pragma unroll
-      for (int it = 0; it < ITER4; it++) {
-        bool any = false;
-#pragma unroll
-        for (int m = 0; m < 4; m++) any = any || (uint32_t)(tw[m] + it * ROWS4) < tlw;
-        lv4[it] = __builtin_amdgcn_raw_buffer_load_b128(rV, any ? base * 4u : kNoOffset, 0, 0);
-        lc4[it] = __builtin_amdgcn_raw_buffer_load_b32(rB, any ? base : kNoOffset, 0, 0);
-        base = wrap_col(base + (uint32_t)(ROWS4 * N), (int)NN);  // ROWS4 rows down, wrapping around the plane
+      for (int it = 0; it < ITER; it++) {
+        const uint32_t idx = (uint32_t)t < tl ? rel : kNoRecord;
+        lv[it] = buffer_load_u32(bV, idx, 0, 0, 0);
+        lc[it] = buffer_load_u8(bB, idx, 0, 0, 0);
+        t += ROWS;
+        rel = wrap_col(rel + (uint32_t)(ROWS * N), (int)NN);  // ROWS rows down, wrapping around the plane
       }
-#pragma unroll
-      for (int it = 0; it < ITER4; it++) {
-#pragma unroll
-        for (int m = 0; m < 4; m++) {
-          const int t = tw[m] + it * ROWS4;
-          const int kj = 4 * gw + (dir ? m : 3 - m);
-          const bool own = (uint32_t)t < tlw;
-          tV[own ? (uint32_t)(t * PITCH + kj) : (uint32_t)(LINES * PITCH + kj)] = lv4[it][m];
-          tB[own ? (uint32_t)(t * PITCH_B + kj) : (uint32_t)(LINES * PITCH_B + kj)] = (uint8_t)(lc4[it] >> (8 * m));
-        }
-      }
-    } else {
-      uint32_t lv[ITER], lc[ITER];
-      {
-        uint32_t rel = rel0;
-        int t = t0;
-#pragma unroll
-        for (int it = 0; it < ITER; it++) {
-          const uint32_t idx = (uint32_t)t < tl ? rel : kNoRecord;
-          lv[it] = buffer_load_u32(bV, idx, 0, 0, 0);
-          lc[it] = buffer_load_u8(bB, idx, 0, 0, 0);
-          t += ROWS;
-          rel = wrap_col(rel + (uint32_t)(ROWS * N), (int)NN);  // ROWS rows down, wrapping around the plane
-        }
-      }
+    }
+    {
       // the slots are recomputed rather than kept from the loads (registers)
       int t = t0;
       asm volatile("" : "+v"(t));
@@ -677,38 +628,7 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
     __syncthreads();
 
     // store the band back (cells no line owns have no record: dropped)
-    if (WIDE) {
-      // the same 4-column groups as the loads: a group the tile owns whole
-      // goes back in one 16-byte store, a partly owned one cell by cell
-      const bool grp_ok = 4 * gw < nq;
-      const int cw = grp_ok ? (dir ? (k0 + 4 * gw) : (N - 4 - k0 - 4 * gw)) : 0;
-      const uint32_t tlw = grp_ok ? (uint32_t)t_lim : 0u;
-      int rw = band0 + r0w;
-      rw -= (rw >= N) ? N : 0;
-      uint32_t base = (uint32_t)rw * (uint32_t)N + (uint32_t)cw;
-      int tw[4];
-#pragma unroll
-      for (int m = 0; m < 4; m++) tw[m] = r0w + bmin - sk[cw + m];
-#pragma unroll
-      for (int it = 0; it < ITER4; it++) {
-        u32x4 val;
-        bool own[4], all = true;
-#pragma unroll
-        for (int m = 0; m < 4; m++) {
-          const int t = tw[m] + it * ROWS4;
-          const int kj = 4 * gw + (dir ? m : 3 - m);
-          own[m] = (uint32_t)t < tlw;
-          all = all && own[m];
-          val[m] = tV[own[m] ? (uint32_t)(t * PITCH + kj) : (uint32_t)(LINES * PITCH + kj)];
-        }
-        __builtin_amdgcn_raw_buffer_store_b128(val, rV, all ? base * 4u : kNoOffset, 0, 0);
-        if (!all) {
-#pragma unroll
-          for (int m = 0; m < 4; m++) buffer_store_u32(val[m], bV, own[m] ? base + (uint32_t)m : kNoRecord, 0, 0, 0);
-        }
-        base = wrap_col(base + (uint32_t)(ROWS4 * N), (int)NN);
-      }
-    } else {
+    {
       uint32_t rel = rel0;
       int t = t0;
       asm volatile("" : "+v"(t), "+v"(rel));
@@ -721,6 +641,336 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
       }
     }
     if (BUFS == 1) __syncthreads();  // every wave has read the tile before the next chunk writes it
+  }
+}
+
+// x-major straights on grids of at least 32 cells: the same 64 lines and
+// chunks of 32 columns, with the band kept in LDS in its memory layout (band
+// row by band row) rather than transposed on the way in.  A thread moves 4
+// adjacent columns of a band row (one 16-byte load of values, one 4-byte
+// load of codes) into 4 consecutive LDS words and one code word, with no
+// per-cell arithmetic; the scan reads line t's cell of column c at band row
+// t + B(c) - bmin, an offset that is the same for every line of the column,
+// so a column read is one address per lane plus a wave-uniform offset.
+// Rows of 33 value words and 9 code words: the 64 lines of one column sit in
+// consecutive band rows, which an odd pitch spreads over distinct banks.
+// The stores read the band back the same way: one 16-byte store where the
+// tile owns all 4 cells of a group, cell by cell where it owns some of them
+// (a group of a band row can hold the last lines of this tile and the first
+// of the next).  PREF: the next chunk's band is loaded into registers while
+// the current one is scanned and stored, so each workgroup keeps loads in
+// flight through its whole loop.
+// A job's tables are global memory; saying so lets the compiler read them
+// with global rather than generic loads (a job read from a batched job
+// table otherwise reaches them through generic pointers).
+template <typename T>
+using GlobalPtr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ GlobalPtr<T> as_global(T* p) {
+  return (GlobalPtr<T>)p;
+}
+
+template <int Q_, int NT, int BUFS>
+struct XBand {
+  static constexpr int Q = Q_;                          // chunk columns
+  static constexpr int NW = NT / 64;                    // waves
+  static constexpr int SUB = 8;                         // columns a wave scans
+  static constexpr int WPG = Q / SUB;                   // waves per group of 64 lines
+  static constexpr int LINES = 64 * (NW / WPG);         // lines of a tile
+  static constexpr int GW = Q / 4;                      // 4-column groups per band row
+  static constexpr int ROWS = NT / GW;                  // band rows per load round
+  static constexpr int BROWS = LINES + Q;               // band rows held (at least LINES + Q - 1)
+  static constexpr int ITER = (BROWS + ROWS - 1) / ROWS;  // load rounds
+  static constexpr int PV = Q + 1;                      // value words per band row (odd)
+  static constexpr int PBW = Q / 4 + 1;                 // code words per band row (odd)
+  uint32_t tV[BUFS][BROWS * PV];
+  uint32_t tB[BUFS][BROWS * PBW];
+  uint32_t aggD[NW][64];
+  uint32_t aggC[NW][64];
+  uint32_t wlut[256];
+  alignas(16) int16_t skew[1024];  // B(c, T) of this plane (read 8 entries at a time)
+  int16_t first_col[1024];         // first column c with |B(c) - B(0)| = i (B is monotone in unit steps)
+};
+
+// Where this thread's group of 4 columns sits in a chunk's band: record
+// index of its cell in band row r0, and the line (relative to the tile) that
+// owns each of its 4 cells in that row (one more per ROWS rows down).
+struct BandGroup {
+  uint32_t base;
+  int lo, hi;  // smallest and largest owner: the owners of a group form a run of consecutive lines
+  bool ok;     // the group lies inside the chunk's columns
+};
+
+template <int Q_, int NT, int BUFS, bool PREF>
+__device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XBand<Q_, NT, BUFS>& sh) {
+  using X = XBand<Q_, NT, BUFS>;
+  constexpr int Q = X::Q, LINES = X::LINES, NW = X::NW, GW = X::GW, ROWS = X::ROWS, ITER = X::ITER;
+  constexpr int PV = X::PV, PBW = X::PBW, BROWS = X::BROWS, SUB = X::SUB, WPG = X::WPG;
+  static_assert(BUFS == 1 || BUFS == 2, "one or two band buffers");
+  static_assert(NT % GW == 0 && Q % SUB == 0 && NW % WPG == 0, "groups tile the threads; columns split over the waves");
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int csec = wave % WPG;            // this wave's column section of a chunk (SUB columns)
+  const int gfirst = wave - csec;         // first wave of this wave's group of 64 lines
+  const int line = (wave / WPG) * 64 + lane;  // the line this lane scans (relative to the tile)
+  const int N = a.N;
+  const uint32_t NN = (uint32_t)N * (uint32_t)N;
+  const int x0 = (tile % a.tiles_x) * LINES;
+  const int T = as_global(a.planes)[tile / a.tiles_x];
+  // this plane's values (by byte offset for 16-byte access, by record for
+  // single cells) and codes (by byte offset)
+  const __amdgpu_buffer_rsrc_t rV =
+      __builtin_amdgcn_make_buffer_rsrc(a.V + (size_t)T * NN, (short)0, (int)(NN * 4u), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t bV =
+      __builtin_amdgcn_make_buffer_rsrc(a.V + (size_t)T * NN, (short)4, (int)NN, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rB =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.B) + (size_t)T * NN, (short)0, (int)NN, kBufferWord3);
+  const uint32_t Lq = as_global(a.edge_len)[T];
+  for (int c = tid; c < 256; c += NT) sh.wlut[c] = weight((uint32_t)c, 256u * Lq + 128u, 4u * Lq);
+  const int dir = (as_global(a.fwd)[T] > 0) == (a.mu_forward != 0);
+  const GlobalPtr<const int16_t> skg = as_global(a.skew) + (size_t)T * N;
+  const int b0 = skg[0];
+  const bool incr = skg[N - 1] >= b0;  // B ascends with the column (else descends)
+  for (int c = tid; c < N; c += NT) {
+    const int b = skg[c];
+    sh.skew[c] = (int16_t)b;
+    if (c == 0 || b != skg[c - 1]) sh.first_col[b >= b0 ? b - b0 : b0 - b] = (int16_t)c;
+  }
+  __syncthreads();
+  const int16_t* sk = sh.skew;
+  const int gw = tid % GW;  // column group of this thread in the load and store phases
+  const int r0 = tid / GW;  // first band row of this thread; rows r0 + it * ROWS
+  const int gs = dir ? gw : GW - 1 - gw;  // the group's place in the band row (memory order)
+  const int t_lim = (N - x0) < LINES ? (N - x0) : LINES;  // lines of this tile inside the grid
+  constexpr uint32_t kNoRecord = 0xFFFFFFFFu;
+  constexpr uint32_t kNoOffset = 0xFFFFFFF0u;  // past the end of either plane: loads nothing
+
+  // chunk k0 walks memory columns k0 .. k0 + nq - 1 (dir) or N - 1 - k0
+  // down to N - k0 - nq; band row 0 is grid row x0 + bmin (mod N), where
+  // bmin is the smallest B over the chunk (B is monotone: at one end)
+  // grid row of band row 0: x0 + bmin reduced mod N (|B| < N, x0 < N)
+  auto band_row0 = [&](int bmin) {
+    int row = x0 + bmin;
+    row += (row < 0) ? N : 0;
+    return row - (row >= N ? N : 0);
+  };
+  // (and brange, the difference of B between the chunk's ends)
+  auto chunk_bmin = [&](int k0, int nq, int& brange) {
+    const int b_first = sk[dir ? k0 : (N - 1 - k0)];
+    const int b_last = sk[dir ? (k0 + nq - 1) : (N - k0 - nq)];
+    brange = __builtin_amdgcn_readfirstlane(b_first < b_last ? b_last - b_first : b_first - b_last);
+    return __builtin_amdgcn_readfirstlane(b_first < b_last ? b_first : b_last);
+  };
+  auto group_of = [&](int k0, int nq, int bmin, BandGroup& g) {
+    g.ok = 4 * gw < nq;
+    const int cw = g.ok ? (dir ? (k0 + 4 * gw) : (N - 4 - k0 - 4 * gw)) : 0;
+    const int row = band_row0(bmin) + r0;  // r0 < ROWS <= N: at most one wrap
+    g.base = (uint32_t)(row - (row >= N ? N : 0)) * (uint32_t)N + (uint32_t)cw;
+    const int t_0 = r0 + bmin - sk[cw], t_3 = r0 + bmin - sk[cw + 3];  // owners of the outer cells
+    g.lo = t_0 < t_3 ? t_0 : t_3;
+    g.hi = t_0 < t_3 ? t_3 : t_0;
+  };
+  // a group some line of the tile owns in band row r0 + it ROWS is loaded;
+  // the others load nothing
+  auto load_band = [&](const BandGroup& g, u32x4 (&lv)[ITER], uint32_t (&lc)[ITER]) {
+    uint32_t base = g.base;
+#pragma unroll
+    for (int it = 0; it < ITER; it++) {
+      if (BROWS % ROWS != 0 && r0 + it * ROWS >= BROWS) break;  // past the rows held (uniform per wave)
+      const bool any = g.ok && g.hi + it * ROWS >= 0 && g.lo + it * ROWS < t_lim;
+      lv[it] = __builtin_amdgcn_raw_buffer_load_b128(rV, any ? base * 4u : kNoOffset, 0, 0);
+      lc[it] = __builtin_amdgcn_raw_buffer_load_b32(rB, any ? base : kNoOffset, 0, 0);
+      base = wrap_col(base + (uint32_t)(ROWS * N), (int)NN);  // ROWS rows down, wrapping around the plane
+    }
+  };
+  auto put_band = [&](int buf, const u32x4 (&lv)[ITER], const uint32_t (&lc)[ITER]) {
+    uint32_t* dv = sh.tV[buf] + r0 * PV + 4 * gs;
+    uint32_t* db = sh.tB[buf] + r0 * PBW + gs;
+#pragma unroll
+    for (int it = 0; it < ITER; it++) {
+      if (BROWS % ROWS != 0 && r0 + it * ROWS >= BROWS) break;
+#pragma unroll
+      for (int m = 0; m < 4; m++) dv[it * ROWS * PV + m] = lv[it][m];
+      db[it * ROWS * PBW] = lc[it];
+    }
+  };
+
+  u32x4 lv[ITER];
+  uint32_t lc[ITER];
+  BandGroup g;
+  int nq = N < Q ? N : Q;
+  int brange;
+  int bmin = chunk_bmin(0, nq, brange);
+  group_of(0, nq, bmin, g);
+  if (PREF) load_band(g, lv, lc);
+  uint32_t carry = kInf;  // value carried along line x0 + line into the chunk
+  int buf = 0;
+  for (int k0 = 0; k0 < N; k0 += Q, buf = (BUFS == 2) ? (buf ^ 1) : 0) {
+    if (!PREF) load_band(g, lv, lc);
+    put_band(buf, lv, lc);
+    // groups the tile owns in part (the last lines of this tile and the
+    // first of the next, or the reverse, in one band row): a band row's
+    // owned cells run between two columns, where B(c) - bmin passes the row
+    // (first line) and the row minus t_lim (past the last line), and those
+    // lie inside the chunk only for the first brange rows after band row 0
+    // and after band row t_lim.  One lane of the last wave per such (row,
+    // edge) finds the column from the first-column table (here, so that the
+    // read overlaps the scan) and, when it falls inside a group, writes that
+    // group's owned cells one by one after the whole groups are stored; the
+    // other waves store whole groups only.
+    int pg_slot = -1;       // LDS slot of the partial group's first cell (-1: none)
+    uint32_t pg_rec = 0;    // its record index
+    uint32_t pg_own = 0;    // owned cells of the group, bit m for memory column gm + m
+    if (wave == NW - 1) {
+      const int r = lane & 31;
+      if (r < brange) {  // uniform per half-wave
+        const bool last = lane >= 32;
+        const int rho = last ? t_lim + r : r;
+        // |B - B(0)| at the first column past the edge, in memory order
+        const int v = last ? (incr ? r + 1 + bmin - b0 : b0 - (r + bmin))
+                           : (incr ? rho + bmin + 1 - b0 : b0 - (rho + bmin));
+        const int cb = sh.first_col[v];
+        if (cb & 3) {
+          const int gm = cb & ~3;  // memory column of the group
+          int row = band_row0(bmin) + rho;
+          while (row >= N) row -= N;  // rho < BROWS: at most BROWS / N + 1 wraps
+          pg_rec = (uint32_t)row * (uint32_t)N + (uint32_t)gm;
+          pg_slot = rho * PV + (gm - (dir ? k0 : (N - k0 - Q)));
+          // the cells before cb are owned when ownership stops there (the
+          // first line's edge with B ascending, the last line's with B
+          // descending), else the cells from cb on
+          const uint32_t before = (1u << (cb & 3)) - 1u;
+          pg_own = (last != incr) ? before : (0xFu & ~before);
+        }
+      }
+    }
+    BandGroup gn;
+    int nq_n = 0, bmin_n = 0, brange_n = 0;
+    if (PREF && k0 + Q < N) {
+      nq_n = (N - k0 - Q) < Q ? (N - k0 - Q) : Q;
+      bmin_n = chunk_bmin(k0 + Q, nq_n, brange_n);
+      group_of(k0 + Q, nq_n, bmin_n, gn);
+      load_band(gn, lv, lc);
+    }
+    __syncthreads();
+
+    // scan: wave w takes chunk columns [w SUB, (w+1) SUB) for all 64 lines;
+    // line `lane` at chunk column k is band row lane + B(c_k) - bmin.  A
+    // chunk's column count is a multiple of 8 (so is N), so a wave's columns
+    // are all inside the chunk or all past it (an identity section).
+    const bool wok = csec * SUB < nq;  // uniform
+    const uint32_t* tV = sh.tV[buf];
+    const uint8_t* tB = reinterpret_cast<const uint8_t*>(sh.tB[buf]);
+    uint32_t u[SUB], w[SUB];
+    int soff[SUB];  // wave-uniform part of each column's value slot
+    if (wok) {
+      // the wave's 8 columns are 8 consecutive entries of the skew table
+      // (ascending when dir, else descending), 16-byte aligned: one read,
+      // unpacked in scalar registers
+      const int cs = dir ? (k0 + csec * SUB) : (N - SUB - k0 - csec * SUB);
+      const uint4 s8 = *reinterpret_cast<const uint4*>(sk + cs);
+      const uint32_t sw[4] = {(uint32_t)__builtin_amdgcn_readfirstlane((int)s8.x),
+                              (uint32_t)__builtin_amdgcn_readfirstlane((int)s8.y),
+                              (uint32_t)__builtin_amdgcn_readfirstlane((int)s8.z),
+                              (uint32_t)__builtin_amdgcn_readfirstlane((int)s8.w)};
+      int offb[SUB];
+#pragma unroll
+      for (int q = 0; q < SUB; q++) {
+        const int k = csec * SUB + q;
+        const int e = dir ? q : (SUB - 1 - q);
+        const int o = (int)(int16_t)(sw[e >> 1] >> (16 * (e & 1))) - bmin;  // band row of line 0
+        const int pos = dir ? k : (Q - 1 - k);                              // column in the band row
+        soff[q] = o * PV + pos;
+        offb[q] = line * (4 * PBW) + (o * (4 * PBW) + pos);
+      }
+      uint32_t code[SUB];
+#pragma unroll
+      for (int q = 0; q < SUB; q++) {
+        u[q] = tV[line * PV + soff[q]];
+        code[q] = tB[offb[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < SUB; q++) w[q] = sh.wlut[code[q]];
+    } else {
+#pragma unroll
+      for (int q = 0; q < SUB; q++) {
+        u[q] = kInf;
+        w[q] = 0u;
+        soff[q] = 0;
+      }
+    }
+    uint32_t D = 0, C = kInf;
+#pragma unroll
+    for (int q = 0; q < SUB; q++) {
+      C = sadd(umin(C, sadd(u[q], a.ct)), w[q]);
+      D = sadd(D, w[q]);
+    }
+    sh.aggD[wave][lane] = D;
+    sh.aggC[wave][lane] = C;
+    __syncthreads();
+    uint32_t v = carry;
+    for (int s = gfirst; s < wave; s++) v = umin(sadd(v, sh.aggD[s][lane]), sh.aggC[s][lane]);
+    if (wok) {
+      uint32_t* tVw = sh.tV[buf];
+      int lpv = line * PV;
+      asm volatile("" : "+v"(lpv));  // the slots are recomputed here rather than kept from the reads (registers)
+#pragma unroll
+      for (int q = 0; q < SUB; q++) {
+        tVw[lpv + soff[q]] = umin(v, u[q]) | (uint32_t)((int32_t)w[q] >> 31);
+        v = sadd(umin(v, sadd(u[q], a.ct)), w[q]);
+      }
+    }
+    for (int s = gfirst; s < gfirst + WPG; s++) carry = umin(sadd(carry, sh.aggD[s][lane]), sh.aggC[s][lane]);
+    __syncthreads();
+
+    // store the band: a group the tile owns whole in one 16-byte store, then
+    // the owned cells of the partly owned groups found above
+    {
+      uint32_t pv[4];
+      if (pg_slot >= 0) {
+#pragma unroll
+        for (int m = 0; m < 4; m++) pv[m] = sh.tV[buf][pg_slot + m];
+      }
+      const uint32_t* sv = sh.tV[buf] + r0 * PV + 4 * gs;
+      uint32_t base = g.base;
+#pragma unroll
+      for (int it = 0; it < ITER; it++) {
+        if (BROWS % ROWS != 0 && r0 + it * ROWS >= BROWS) break;
+        u32x4 val;
+#pragma unroll
+        for (int m = 0; m < 4; m++) val[m] = sv[it * ROWS * PV + m];
+        const bool all = g.ok && g.lo + it * ROWS >= 0 && g.hi + it * ROWS < t_lim;
+        __builtin_amdgcn_raw_buffer_store_b128(val, rV, all ? base * 4u : kNoOffset, 0, 0);
+        base = wrap_col(base + (uint32_t)(ROWS * N), (int)NN);
+      }
+      if (pg_slot >= 0) {
+        // the owned cells are a run of 1 to 3 at one end of the group: one
+        // store of the run's length (each cell a separate memory request
+        // costs more than the cells' bytes)
+        const int m0 = __builtin_ctz(pg_own), len = __builtin_popcount(pg_own);
+        const uint32_t off = (pg_rec + (uint32_t)m0) * 4u;
+        const uint32_t a0 = m0 ? pv[1] : pv[0];
+        const uint32_t a1 = m0 == 0 ? pv[1] : (m0 == 1 ? pv[2] : pv[3]);
+        const uint32_t a2 = m0 ? pv[3] : pv[2];
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+        if (len == 1) __builtin_amdgcn_raw_buffer_store_b32(m0 == 3 ? pv[3] : (m0 == 2 ? pv[2] : a0), rV, off, 0, 0);
+        if (len == 2) __builtin_amdgcn_raw_buffer_store_b64(u32x2{m0 ? pv[2] : pv[0], m0 ? pv[3] : pv[1]}, rV, off, 0, 0);
+        if (len == 3) __builtin_amdgcn_raw_buffer_store_b96(u32x3{a0, a1, a2}, rV, off, 0, 0);
+      }
+    }
+    if (BUFS == 1) __syncthreads();  // every wave has read the band before the next chunk writes it
+    if (PREF) {
+      g = gn;
+      nq = nq_n;
+      bmin = bmin_n;
+      brange = brange_n;
+    } else if (k0 + Q < N) {
+      nq = (N - k0 - Q) < Q ? (N - k0 - Q) : Q;
+      bmin = chunk_bmin(k0 + Q, nq, brange);
+      group_of(k0 + Q, nq, bmin, g);
+    }
   }
 }
 
@@ -786,29 +1036,63 @@ int row_grid(int blocks, int waves, int P) {
 // x-major workgroups stay resident too.  A tile's stores read only the LDS
 // band, and the next tile writes its band after the barrier that follows its
 // weight and skew tables, so a wave still storing never sees it overwritten.
-// (six workgroups of NT threads per CU fit the LDS: ask the register
-// allocator for the occupancy that allows)
-template <int Q, int NT, int BUFS, bool WIDE>
+// Grids of at least 32 cells take band tiles (xmajor_band_tile), smaller
+// ones the transposed tile.  Occupancy asked of the register allocator: the
+// waves per SIMD that the LDS allows.
+constexpr int XBQ = 32;          // band tiles: chunk columns
+constexpr int XBNT = 256;        // band tiles: workgroup threads
+constexpr bool XBPREF = false;   // band tiles: load the next chunk while scanning this one
+constexpr int kLdsBytes = 160 * 1024;
+
+// (at most 7 waves per SIMD: the tile needs about 70 registers)
+template <int Q, int NT, int BUFS>
+constexpr int xband_wg_per_cu() {
+  const int by_lds = kLdsBytes / (int)sizeof(XBand<Q, NT, BUFS>);
+  const int by_waves = 28 / (NT / 64);
+  return by_lds < by_waves ? by_lds : by_waves;
+}
+template <int Q, int NT, int BUFS>
+constexpr int xband_waves_per_simd() { return xband_wg_per_cu<Q, NT, BUFS>() * (NT / 64) / 4; }
+
+template <int Q, int NT, int BUFS>
+__global__ __launch_bounds__(NT, (xband_waves_per_simd<Q, NT, BUFS>())) void xmajor_band_kernel(SweepJob job) {
+  __shared__ XBand<Q, NT, BUFS> sh;
+  for (int b = blockIdx.x; b < job.blocks; b += gridDim.x)
+    xmajor_band_tile<Q, NT, BUFS, XBPREF>(job, tile_of(b, job.blocks, job.order), sh);
+}
+
+template <int Q, int NT, int BUFS>
+__global__ __launch_bounds__(NT, (xband_waves_per_simd<Q, NT, BUFS>())) void xmajor_band_batch_kernel(
+    const SweepJob* __restrict__ jobs, int n_jobs, int order) {
+  __shared__ XBand<Q, NT, BUFS> sh;
+  const int t = tile_of(blockIdx.x, gridDim.x, order);
+  const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
+  const SweepJob job = jobs[j];
+  xmajor_band_tile<Q, NT, BUFS, XBPREF>(job, t - job.first_block, sh);
+}
+
+// (six transposed tiles of 27 KB fit a CU)
+template <int Q, int NT, int BUFS>
 __global__ __launch_bounds__(NT, 6) void xmajor_sweep_kernel(SweepJob job) {
   __shared__ XShared<Q, NT, BUFS> sh;
   for (int b = blockIdx.x; b < job.blocks; b += gridDim.x)
-    xmajor_sweep_tile<Q, NT, BUFS, WIDE>(job, tile_of(b, job.blocks, job.order), sh);
+    xmajor_sweep_tile<Q, NT, BUFS>(job, tile_of(b, job.blocks, job.order), sh);
 }
 
-// Resident x-major workgroups: 8 per CU (about what fits at once).
-int xmajor_grid(int blocks) {
-  const int cap = 256 * knob(NHP_KNOB_XMAJOR_WG_PER_CU, 8);
-  return blocks < cap ? blocks : cap;
-}
-
-template <int Q, int NT, int BUFS, bool WIDE>
+template <int Q, int NT, int BUFS>
 __global__ __launch_bounds__(NT, 6) void xmajor_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs,
-                                                                 int order) {
+                                                                  int order) {
   __shared__ XShared<Q, NT, BUFS> sh;
   const int t = tile_of(blockIdx.x, gridDim.x, order);
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
   const SweepJob job = jobs[j];
-  xmajor_sweep_tile<Q, NT, BUFS, WIDE>(job, t - job.first_block, sh);
+  xmajor_sweep_tile<Q, NT, BUFS>(job, t - job.first_block, sh);
+}
+
+// Resident x-major workgroups: what fits a CU at once, times 256 CUs.
+int xmajor_grid(int blocks, int per_cu) {
+  const int cap = 256 * knob(NHP_KNOB_XMAJOR_WG_PER_CU, per_cu);
+  return blocks < cap ? blocks : cap;
 }
 
 __global__ void init_kernel(uint32_t* __restrict__ V, size_t n4, uint32_t start) {
@@ -857,17 +1141,21 @@ __global__ void walls_kernel(uint8_t* __restrict__ B, int N, int L) {
   }
 }
 
-// x-major chunks of 32 columns, 256 threads per workgroup (64 columns with
-// 512 threads and 32 columns with 512 threads measured slower)
+// transposed x-major tiles (grids under 32 cells): chunks of 32 columns,
+// 256 threads per workgroup
 constexpr int XQ = 32;   // x-major chunk columns
 constexpr int XNT = 256;  // x-major workgroup threads
 constexpr int XBUFS_BUILTIN = 2;  // x-major tile buffers unless a knob says otherwise
+constexpr int XB_BUFS_BUILTIN = 1;  // the same for band tiles
 
 }  // namespace
 
-// Whether the x-major kernel takes 4-column loads for grids of side N: a load
-// round covers XNT / (XQ / 4) band rows, which must not exceed N (one wrap).
-bool xmajor_wide(int N) { return N >= XNT / (XQ / 4); }
+// Whether the x-major kernel takes band tiles for grids of side N: a load
+// round covers XBNT / (XBQ / 4) band rows, which must not exceed N (one wrap).
+bool xmajor_wide(int N) { return N >= XBNT / (XBQ / 4); }
+
+// Lines per x-major tile for grids of side N.
+int xmajor_lines(int N) { return xmajor_wide(N) ? XBand<XBQ, XBNT, 1>::LINES : 64; }
 
 namespace {
 
@@ -955,7 +1243,8 @@ int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj) 
     y.planes = d.planes + d.n_planes_x;
     y.blocks = tiles_x * d.n_planes_y;
     x.planes = d.planes;
-    x.blocks = tiles_x * d.n_planes_x;
+    x.tiles_x = (N + xmajor_lines(N) - 1) / xmajor_lines(N);
+    x.blocks = x.tiles_x * d.n_planes_x;
     x.P = 0;
     row->blocks = 0;
     xmaj->blocks = 0;
@@ -1047,12 +1336,23 @@ hipError_t launch_sweep_part(const DevPlan& d, Pass pass, int parts, hipStream_t
     if (e != hipSuccess) return e;
   }
   if (xmaj.blocks && (parts & 2)) {
-    const dim3 grid(xmajor_grid(xmaj.blocks)), block(XNT);
-    const bool one = knob(NHP_KNOB_XMAJOR_BUFFERS, XBUFS_BUILTIN) == 1, wide = xmajor_wide(xmaj.N);
-    if (one && wide) hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 1, true>), grid, block, 0, s, xmaj);
-    if (one && !wide) hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 1, false>), grid, block, 0, s, xmaj);
-    if (!one && wide) hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 2, true>), grid, block, 0, s, xmaj);
-    if (!one && !wide) hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 2, false>), grid, block, 0, s, xmaj);
+    const bool wide = xmajor_wide(xmaj.N);
+    const bool one = knob(NHP_KNOB_XMAJOR_BUFFERS, wide ? XB_BUFS_BUILTIN : XBUFS_BUILTIN) == 1;
+    if (wide) {
+      const dim3 block(XBNT);
+      if (one)
+        hipLaunchKernelGGL((xmajor_band_kernel<XBQ, XBNT, 1>),
+                           dim3(xmajor_grid(xmaj.blocks, xband_wg_per_cu<XBQ, XBNT, 1>())), block, 0, s, xmaj);
+      else
+        hipLaunchKernelGGL((xmajor_band_kernel<XBQ, XBNT, 2>),
+                           dim3(xmajor_grid(xmaj.blocks, xband_wg_per_cu<XBQ, XBNT, 2>())), block, 0, s, xmaj);
+    } else {
+      const dim3 grid(xmajor_grid(xmaj.blocks, 6)), block(XNT);
+      if (one)
+        hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 1>), grid, block, 0, s, xmaj);
+      else
+        hipLaunchKernelGGL((xmajor_sweep_kernel<XQ, XNT, 2>), grid, block, 0, s, xmaj);
+    }
     return hipGetLastError();
   }
   return hipSuccess;
@@ -1096,13 +1396,17 @@ hipError_t launch_sweep_batch(const SweepJob* d_jobs, int n_jobs, int total_bloc
   if (n_jobs == 0) return hipSuccess;
   if (xmajor) {
     const int order = knob(NHP_KNOB_TILE_ORDER, 1);
-    const bool one = knob(NHP_KNOB_XMAJOR_BUFFERS, XBUFS_BUILTIN) == 1;
-    const dim3 grid(total_blocks), block(XNT);
-    // (for x-major launches `pow2` says every job's grid takes 4-column loads)
-    if (one && pow2) hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 1, true>), grid, block, 0, s, d_jobs, n_jobs, order);
-    if (one && !pow2) hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 1, false>), grid, block, 0, s, d_jobs, n_jobs, order);
-    if (!one && pow2) hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 2, true>), grid, block, 0, s, d_jobs, n_jobs, order);
-    if (!one && !pow2) hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 2, false>), grid, block, 0, s, d_jobs, n_jobs, order);
+    const bool one = knob(NHP_KNOB_XMAJOR_BUFFERS, pow2 ? XB_BUFS_BUILTIN : XBUFS_BUILTIN) == 1;
+    const dim3 grid(total_blocks);
+    // (for x-major launches `pow2` says every job's grid takes band tiles)
+    if (pow2 && one)
+      hipLaunchKernelGGL((xmajor_band_batch_kernel<XBQ, XBNT, 1>), grid, dim3(XBNT), 0, s, d_jobs, n_jobs, order);
+    if (pow2 && !one)
+      hipLaunchKernelGGL((xmajor_band_batch_kernel<XBQ, XBNT, 2>), grid, dim3(XBNT), 0, s, d_jobs, n_jobs, order);
+    if (!pow2 && one)
+      hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 1>), grid, dim3(XNT), 0, s, d_jobs, n_jobs, order);
+    if (!pow2 && !one)
+      hipLaunchKernelGGL((xmajor_sweep_batch_kernel<XQ, XNT, 2>), grid, dim3(XNT), 0, s, d_jobs, n_jobs, order);
     return hipGetLastError();
   }
   if (waves < 1 || waves > 16) return hipErrorInvalidValue;

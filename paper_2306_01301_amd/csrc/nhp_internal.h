@@ -132,6 +132,7 @@ int make_sweep_jobs(const DevPlan& d, Pass pass, SweepJob* row, SweepJob* xmaj);
 // Whether x-major jobs of grid side N take the 4-column-load kernel (batched
 // x-major launches group their jobs by it and pass it as `pow2`).
 bool xmajor_wide(int N);
+int xmajor_lines(int N);  // lines per x-major tile
 // Row jobs of one launch share P, fused, guard (= L % P != 0) and their
 // wave count (the workgroup size is 64 waves threads); x-major jobs of one
 // launch share xmajor_wide(N), passed as pow2.
