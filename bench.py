@@ -40,7 +40,7 @@ KERNELS = {
     "fused_turn": "row_sweep_kernel<32, true, false, true, true> (two turn maneuvers on shared circles in one launch)",
     "turn": "row_sweep_kernel<32, false, false, true, true> (one turn maneuver)",
     "straight_y": "row_sweep_kernel<32, false, false, true, false> (straight maneuver, y-major planes)",
-    "straight_x": "xmajor_sweep_kernel (straight maneuver, x-major planes)",
+    "straight_x": "xmajor_band_kernel<32, 256, 1> (straight maneuver, x-major planes, band tiles)",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweeps_maze_512.json")
 
@@ -405,6 +405,7 @@ def main() -> int:
                     help="first run one plain device copy of 1 GiB (counter calibration)")
     ap.add_argument("--skip-batch", action="store_true", help="skip the batched-vs-single comparison")
     ap.add_argument("--skip-serving", action="store_true", help="skip the serving block")
+    ap.add_argument("--skip-other", action="store_true", help="skip the parking_256 and plain_64 lines")
     ap.add_argument("--skip-check", action="store_true", help="skip the check against sweep_n_turns")
     ap.add_argument("--serve-rates", default="20,200", help="serving block: Poisson rates in plans/s")
     ap.add_argument("--serve-requests", type=int, default=300, help="serving block: requests per rate")
@@ -597,7 +598,8 @@ def main() -> int:
                                      / 1e9 / HBM_PEAK_GBS}},
     }
     p.close()
-    out["other_workloads"] = other_workloads()
+    if not args.skip_other:
+        out["other_workloads"] = other_workloads()
     if not args.skip_batch:
         out["latency_ms"]["batch_64"] = batch_comparison()
     if not args.skip_serving:

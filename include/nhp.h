@@ -356,7 +356,8 @@ enum nhp_knob {
   NHP_KNOB_XMAJOR_WG_PER_CU = 1, /* the same for the x-major straight launches, 1..16 */
   NHP_KNOB_TILE_ORDER = 2,       /* 1: tiles that share row segments run on one XCD (its L2); 2: launch order */
   NHP_KNOB_XMAJOR_BUFFERS = 3    /* x-major LDS tiles per workgroup: 2 (the next chunk's loads need no barrier
-                                    after the stores) or 1 (more workgroups fit a compute unit) */
+                                    after the stores) or 1 (more workgroups fit a compute unit); built-in: 1 for
+                                    grids of at least 32 cells (band tiles), 2 below */
 };
 /* Errors: NHP_EINVAL (unknown knob or value out of range). */
 int nhp_set_knob(uint32_t knob, int32_t value);

@@ -72,7 +72,7 @@ def measure(length: int) -> dict:
 
 KNOB_NAMES = {"row_wg_per_cu": 0, "xmajor_wg_per_cu": 1, "tile_order": 2, "xmajor_buffers": 3}
 KNOB_GRID = {"row_wg_per_cu": (0, 1, 2), "xmajor_wg_per_cu": (0, 4, 6), "tile_order": (0, 2),
-             "xmajor_buffers": (0, 1)}  # 0: the built-in choice (XCD-aware tiles, two x-major tiles)
+             "xmajor_buffers": (0, 2)}  # 0: the built-in choice (XCD-aware tiles, one band tile buffer)
 
 
 def set_knobs(values: dict) -> None:

@@ -1044,11 +1044,15 @@ constexpr int XBNT = 256;        // band tiles: workgroup threads
 constexpr bool XBPREF = false;   // band tiles: load the next chunk while scanning this one
 constexpr int kLdsBytes = 160 * 1024;
 
-// (at most 7 waves per SIMD: the tile needs about 70 registers)
+// Band tiles resident per CU: what the LDS allows, at most 20 waves.  More
+// (the LDS allows 28 waves of 4-wave tiles with one buffer) gain no time and
+// evict band rows that neighbouring tiles share from the L2 before both have
+// read them: 1.15 times the algorithmic fetch at 6 or 7 tiles per CU against
+// 1.04 at 5.
 template <int Q, int NT, int BUFS>
 constexpr int xband_wg_per_cu() {
   const int by_lds = kLdsBytes / (int)sizeof(XBand<Q, NT, BUFS>);
-  const int by_waves = 28 / (NT / 64);
+  const int by_waves = 20 / (NT / 64) > 0 ? 20 / (NT / 64) : 1;
   return by_lds < by_waves ? by_lds : by_waves;
 }
 template <int Q, int NT, int BUFS>

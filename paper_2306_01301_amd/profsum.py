@@ -115,7 +115,7 @@ def traffic(fetch_dir: str, write_dir: str, workload: str, copy_bytes: int, comm
         k["launches"] += 1
         k["fetch_bytes"] += fv / fpb
         k["write_bytes"] += wv / wpb
-        if "sweep_kernel" in name:
+        if "sweep_kernel" in name or "band_kernel" in name:
             sweeps.append((short_name(name), fv / fpb, wv / wpb))
     for k in kernels.values():
         k["fetch_bytes"] /= k["launches"]
