@@ -119,6 +119,29 @@ int check_plan(const nhp_plan* plan) {
   return NHP_OK;
 }
 
+// The order in which an x-major launch takes its planes (every plane is
+// swept independently, so only speed depends on it).  A steeper plane has
+// taller bands (64 lines plus the change of B over a chunk), so its tiles
+// take longer.  The planes are dealt, steepest first, round-robin to eight
+// consecutive ranges, one per XCD of the XCD-aware tile order: every XCD
+// gets the same mix and works through its steep planes first, so the flat
+// ones fill the launch's last round.
+std::vector<int32_t> balanced_xmajor_order(const std::vector<int32_t>& planes_x, const std::vector<int16_t>& skew,
+                                           int N) {
+  std::vector<int32_t> by_steepness(planes_x);
+  auto rise = [&](int32_t T) {
+    const int d = skew[(size_t)T * N + N - 1] - skew[(size_t)T * N];
+    return d < 0 ? -d : d;
+  };
+  std::stable_sort(by_steepness.begin(), by_steepness.end(),
+                   [&](int32_t a, int32_t b) { return rise(a) > rise(b); });
+  std::vector<int32_t> out;
+  out.reserve(by_steepness.size());
+  for (size_t x = 0; x < 8; x++)
+    for (size_t i = x; i < by_steepness.size(); i += 8) out.push_back(by_steepness[i]);
+  return out;
+}
+
 }  // namespace
 
 static int finish_extract(nhp_plan* plan, nhp_step* h_steps, uint32_t cap, uint32_t* n_steps, uint32_t* best_ijt,
@@ -211,9 +234,9 @@ int plan_create(const nhp_params* params, void* d_workspace, size_t workspace_by
   }
   d.n_schedule = params->n_schedule;
 
-  std::vector<int32_t> planes(plan->t.planes_x);
-  planes.insert(planes.end(), plan->t.planes_y.begin(), plan->t.planes_y.end());
   const HostTables& t = plan->t;
+  std::vector<int32_t> planes = balanced_xmajor_order(t.planes_x, *t.skew16, (int)params->nx);
+  planes.insert(planes.end(), t.planes_y.begin(), t.planes_y.end());
   struct Up {
     void* dst;
     const void* src;
