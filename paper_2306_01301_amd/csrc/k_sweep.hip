@@ -146,11 +146,19 @@ struct RowShared {
 // GUARD: the curve length is not a multiple of P, so the last section has
 // fewer than P real steps and the steps past the curve are skipped (without
 // it every section is full and the loops carry no conditions).
-template <int P, bool FUSED, bool GUARD, bool POW2>
+// Write elision: a pass changes few poses once the search front has gone
+// by (about 5 % of the poses and 11 % of the 128-byte lines per pass of a
+// 512^3 maze plan), so a wave does not store a step whose 64 values are all
+// unchanged (memory already holds them).  The test is per wave and step: a
+// ballot in the replay, one bit per step, and a uniform branch at the store
+// (no per-lane work; a step with any change stores all its lanes).
+template <int P, bool FUSED, bool GUARD, bool POW2, bool ELIDE>
 __device__ __forceinline__ void scan_section(const SweepJob& a, const RowBuffers& buf, RowShared& sh,
                                              uint32_t (&u)[P], uint32_t (&code)[P], int n_real, int S, int wave,
                                              int lane, bool cyclic, bool active, int xp, int first, int N) {
   uint32_t packed[FUSED ? P / 4 : 1];
+  uint32_t changed = 0;  // bit k: some lane's value at step k changed (wave-uniform)
+  static_assert(!ELIDE || P <= 32, "one bit per step");
   {
     // weights replace the codes; compose the section into (D, C):
     // min(C + w, u + ct + w) = min(C, u + ct) + w (saturating add is monotone).
@@ -191,6 +199,11 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, const RowBuffers
       const uint32_t w = code[k];
       const uint32_t uu = u[k];
       u[k] = FUSED ? umin(v, uu) : (umin(v, uu) | (uint32_t)((int32_t)w >> 31));
+      if (ELIDE) {
+        // fold each step's mask into its bit now (not 32 masks held in registers)
+        changed = (uint32_t)__builtin_amdgcn_readfirstlane(
+            (int)(changed | ((__builtin_amdgcn_ballot_w64(u[k] != uu) != 0ull ? 1u : 0u) << k)));
+      }
       v = sadd(umin(v, sadd(uu, a.ct)), w);
     }
     if (FUSED) {
@@ -218,6 +231,10 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, const RowBuffers
         const uint32_t w = code[k];
         const uint32_t uu = u[k];
         u[k] = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+        if (ELIDE) {
+          changed = (uint32_t)__builtin_amdgcn_readfirstlane(
+              (int)(changed | ((__builtin_amdgcn_ballot_w64(u[k] != uu) != 0ull ? 1u : 0u) << k)));
+        }
         v = sadd(umin(v, sadd(uu, a.ct2)), w);
       }
     }
@@ -228,7 +245,7 @@ __device__ __forceinline__ void scan_section(const SweepJob& a, const RowBuffers
   if (active) {
 #pragma unroll
     for (int k = 0; k < P; k++) {
-      if (!GUARD || k < n_real) {
+      if ((!GUARD || k < n_real) && (!ELIDE || ((changed >> k) & 1u))) {
         buffer_store_u32(u[k], buf.V,
                          row_cell<POW2>(sh.row_base[first + k], (uint32_t)xs, POW2 ? 0u : sh.shift[first + k], N), 0,
                          0, 0);
@@ -475,7 +492,7 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
       code[k] = buffer_load_u8(buf.B, cell, 0, 0, 0);
     }
   }
-  scan_section<P, FUSED, GUARD, POW2>(a, buf, sh, u, code, n_real, S, wave, lane, cyclic, active, xp, first, N);
+  scan_section<P, FUSED, GUARD, POW2, (P <= 32)>(a, buf, sh, u, code, n_real, S, wave, lane, cyclic, active, xp, first, N);
 }
 
 // x-major straights (|tan| <= 1): line x' visits (c, x' + B(c)), so lines
