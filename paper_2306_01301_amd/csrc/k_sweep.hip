@@ -707,6 +707,7 @@ struct XBand {
   uint32_t wlut[256];
   alignas(16) int16_t skew[1024];  // B(c, T) of this plane (read 8 entries at a time)
   int16_t first_col[1024];         // first column c with |B(c) - B(0)| = i (B is monotone in unit steps)
+  uint8_t dirty[2][BROWS];         // band rows holding a changed value, by chunk parity
 };
 
 // Where this thread's group of 4 columns sits in a chunk's band: record
@@ -718,8 +719,11 @@ struct BandGroup {
   bool ok;     // the group lies inside the chunk's columns
 };
 
+// `chunks` counts the chunks this workgroup has swept (across tiles): its
+// parity selects the band-row change flags of a chunk, which start cleared.
 template <int Q_, int NT, int BUFS, bool PREF>
-__device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XBand<Q_, NT, BUFS>& sh) {
+__device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XBand<Q_, NT, BUFS>& sh,
+                                                 uint32_t& chunks) {
   using X = XBand<Q_, NT, BUFS>;
   constexpr int Q = X::Q, LINES = X::LINES, NW = X::NW, GW = X::GW, ROWS = X::ROWS, ITER = X::ITER;
   constexpr int PV = X::PV, PBW = X::PBW, BROWS = X::BROWS, SUB = X::SUB, WPG = X::WPG;
@@ -837,6 +841,7 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
     // group's owned cells one by one after the whole groups are stored; the
     // other waves store whole groups only.
     int pg_slot = -1;       // LDS slot of the partial group's first cell (-1: none)
+    int pg_rho = 0;         // its band row
     uint32_t pg_rec = 0;    // its record index
     uint32_t pg_own = 0;    // owned cells of the group, bit m for memory column gm + m
     if (wave == NW - 1) {
@@ -854,6 +859,7 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
           while (row >= N) row -= N;  // rho < BROWS: at most BROWS / N + 1 wraps
           pg_rec = (uint32_t)row * (uint32_t)N + (uint32_t)gm;
           pg_slot = rho * PV + (gm - (dir ? k0 : (N - k0 - Q)));
+          pg_rho = rho;
           // the cells before cb are owned when ownership stops there (the
           // first line's edge with B ascending, the last line's with B
           // descending), else the cells from cb on
@@ -879,8 +885,15 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
     const bool wok = csec * SUB < nq;  // uniform
     const uint32_t* tV = sh.tV[buf];
     const uint8_t* tB = reinterpret_cast<const uint8_t*>(sh.tB[buf]);
+    // change flags: this chunk's set is clear (it was cleared during the
+    // previous chunk); clear the other set for the next chunk (the previous
+    // chunk's stores read it, and every wave finished them before the
+    // barrier above)
+    const int par = (int)(chunks & 1u);
+    for (int i = tid; i < BROWS; i += NT) sh.dirty[par ^ 1][i] = 0;
     uint32_t u[SUB], w[SUB];
     int soff[SUB];  // wave-uniform part of each column's value slot
+    int orow[SUB];  // band row of line 0 at each column (wave-uniform)
     if (wok) {
       // the wave's 8 columns are 8 consecutive entries of the skew table
       // (ascending when dir, else descending), 16-byte aligned: one read,
@@ -899,6 +912,7 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
         const int o = (int)(int16_t)(sw[e >> 1] >> (16 * (e & 1))) - bmin;  // band row of line 0
         const int pos = dir ? k : (Q - 1 - k);                              // column in the band row
         soff[q] = o * PV + pos;
+        orow[q] = o;
         offb[q] = line * (4 * PBW) + (o * (4 * PBW) + pos);
       }
       uint32_t code[SUB];
@@ -915,6 +929,7 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
         u[q] = kInf;
         w[q] = 0u;
         soff[q] = 0;
+        orow[q] = 0;
       }
     }
     uint32_t D = 0, C = kInf;
@@ -934,7 +949,11 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
       asm volatile("" : "+v"(lpv));  // the slots are recomputed here rather than kept from the reads (registers)
 #pragma unroll
       for (int q = 0; q < SUB; q++) {
-        tVw[lpv + soff[q]] = umin(v, u[q]) | (uint32_t)((int32_t)w[q] >> 31);
+        const uint32_t out = umin(v, u[q]) | (uint32_t)((int32_t)w[q] >> 31);
+        tVw[lpv + soff[q]] = out;
+        // flag the band row of a changed value (most columns change none:
+        // then the wave writes no flag)
+        if (__builtin_amdgcn_ballot_w64(out != u[q]) != 0ull && out != u[q]) sh.dirty[par][line + orow[q]] = 1;
         v = sadd(umin(v, sadd(u[q], a.ct)), w[q]);
       }
     }
@@ -942,9 +961,11 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
     __syncthreads();
 
     // store the band: a group the tile owns whole in one 16-byte store, then
-    // the owned cells of the partly owned groups found above
+    // the owned cells of the partly owned groups found above; a band row
+    // whose values all stayed as loaded is not stored (memory holds them)
     {
       uint32_t pv[4];
+      if (pg_slot >= 0 && !sh.dirty[par][pg_rho]) pg_slot = -1;
       if (pg_slot >= 0) {
 #pragma unroll
         for (int m = 0; m < 4; m++) pv[m] = sh.tV[buf][pg_slot + m];
@@ -958,7 +979,7 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
 #pragma unroll
         for (int m = 0; m < 4; m++) val[m] = sv[it * ROWS * PV + m];
         const bool all = g.ok && g.lo + it * ROWS >= 0 && g.hi + it * ROWS < t_lim;
-        __builtin_amdgcn_raw_buffer_store_b128(val, rV, all ? base * 4u : kNoOffset, 0, 0);
+        if (sh.dirty[par][r0 + it * ROWS]) __builtin_amdgcn_raw_buffer_store_b128(val, rV, all ? base * 4u : kNoOffset, 0, 0);
         base = wrap_col(base + (uint32_t)(ROWS * N), (int)NN);
       }
       if (pg_slot >= 0) {
@@ -978,6 +999,7 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
       }
     }
     if (BUFS == 1) __syncthreads();  // every wave has read the band before the next chunk writes it
+    chunks++;
     if (PREF) {
       g = gn;
       nq = nq_n;
@@ -1078,8 +1100,10 @@ constexpr int xband_waves_per_simd() { return xband_wg_per_cu<Q, NT, BUFS>() * (
 template <int Q, int NT, int BUFS>
 __global__ __launch_bounds__(NT, (xband_waves_per_simd<Q, NT, BUFS>())) void xmajor_band_kernel(SweepJob job) {
   __shared__ XBand<Q, NT, BUFS> sh;
+  for (int i = threadIdx.x; i < 2 * XBand<Q, NT, BUFS>::BROWS; i += NT) sh.dirty[i & 1][i >> 1] = 0;
+  uint32_t chunks = 0;  // (the tile's first barrier orders the clearing before any flag is set)
   for (int b = blockIdx.x; b < job.blocks; b += gridDim.x)
-    xmajor_band_tile<Q, NT, BUFS, XBPREF>(job, tile_of(b, job.blocks, job.order), sh);
+    xmajor_band_tile<Q, NT, BUFS, XBPREF>(job, tile_of(b, job.blocks, job.order), sh, chunks);
 }
 
 template <int Q, int NT, int BUFS>
@@ -1089,7 +1113,9 @@ __global__ __launch_bounds__(NT, (xband_waves_per_simd<Q, NT, BUFS>())) void xma
   const int t = tile_of(blockIdx.x, gridDim.x, order);
   const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
   const SweepJob job = jobs[j];
-  xmajor_band_tile<Q, NT, BUFS, XBPREF>(job, t - job.first_block, sh);
+  for (int i = threadIdx.x; i < 2 * XBand<Q, NT, BUFS>::BROWS; i += NT) sh.dirty[i & 1][i >> 1] = 0;
+  uint32_t chunks = 0;
+  xmajor_band_tile<Q, NT, BUFS, XBPREF>(job, t - job.first_block, sh, chunks);
 }
 
 // (six transposed tiles of 27 KB fit a CU)
