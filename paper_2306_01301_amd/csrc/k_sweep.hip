@@ -268,6 +268,13 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
   constexpr int G = 16;      // codes per load group
   constexpr int H = P / 2;   // values kept in registers
   __shared__ uint32_t upper[16][P - H][64];
+  // write elision, as in scan_section: bit k of changed[k / 32] says some
+  // lane's value at step k changed (wave-uniform)
+  uint32_t changed[(P + 31) / 32] = {};
+  auto note = [&](int k, uint32_t before, uint32_t after) {
+    changed[k >> 5] = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)(changed[k >> 5] | ((__builtin_amdgcn_ballot_w64(after != before) != 0ull ? 1u : 0u) << (k & 31))));
+  };
   uint32_t (*hi)[64] = upper[wave];
   uint32_t u[H], packed[P / 4];
   const int xl = active ? xp : N - 1;
@@ -338,6 +345,7 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
       const uint32_t uu = real ? (k < H ? u[k] : hi[k - H][lane]) : kInf;
       // (a fused pair forces hard poses to INF only in its second replay)
       const uint32_t out = FUSED ? umin(v, uu) : (umin(v, uu) | (uint32_t)((int32_t)w >> 31));
+      note(k, uu, out);
       if (k < H)
         u[k] = out;
       else
@@ -377,6 +385,7 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
       const uint32_t w = real ? weight2_of(k) : 0u;
       const uint32_t uu = real ? (k < H ? u[k] : hi[k - H][lane]) : kInf;
       const uint32_t out = umin(v, uu) | (uint32_t)((int32_t)w >> 31);
+      note(k, uu, out);
       if (k < H)
         u[k] = out;
       else
@@ -390,7 +399,7 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
 #pragma unroll
     for (int k = 0; k < P; k++) {
       if ((k & 7) == 0) asm volatile("" ::: "memory");
-      if (!GUARD || k < n_real) {
+      if ((!GUARD || k < n_real) && ((changed[k >> 5] >> (k & 31)) & 1u)) {
         buffer_store_u32(k < H ? u[k] : hi[k - H][lane], buf.V,
                          row_cell<POW2>(sh.row_base[first + k], (uint32_t)xs, POW2 ? 0u : sh.shift[first + k], N), 0,
                          0, 0);
