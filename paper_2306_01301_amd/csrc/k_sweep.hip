@@ -1089,7 +1089,7 @@ int row_grid(int blocks, int waves, int P) {
 // waves per SIMD that the LDS allows.
 constexpr int XBQ = 32;          // band tiles: chunk columns
 constexpr int XBNT = 256;        // band tiles: workgroup threads
-constexpr bool XBPREF = false;   // band tiles: load the next chunk while scanning this one
+constexpr bool XBPREF = true;    // band tiles: load the next chunk while scanning this one
 constexpr int kLdsBytes = 160 * 1024;
 
 // Band tiles resident per CU: what the LDS allows, at most 20 waves.  More
