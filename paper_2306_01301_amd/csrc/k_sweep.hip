@@ -681,11 +681,13 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
 // Rows of 33 value words and 9 code words: the 64 lines of one column sit in
 // consecutive band rows, which an odd pitch spreads over distinct banks.
 // The stores read the band back the same way: one 16-byte store where the
-// tile owns all 4 cells of a group, cell by cell where it owns some of them
-// (a group of a band row can hold the last lines of this tile and the first
-// of the next).  PREF: the next chunk's band is loaded into registers while
+// tile owns all 4 cells of a group, and one store of the owned run where it
+// owns only some of them (a group of a band row can hold the last lines of
+// this tile and the first of the next); band rows whose values did not change
+// are not stored.  PREF: the next chunk's band is loaded into registers while
 // the current one is scanned and stored, so each workgroup keeps loads in
 // flight through its whole loop.
+
 // A job's tables are global memory; saying so lets the compiler read them
 // with global rather than generic loads (a job read from a batched job
 // table otherwise reaches them through generic pointers).
@@ -720,8 +722,8 @@ struct XBand {
 };
 
 // Where this thread's group of 4 columns sits in a chunk's band: record
-// index of its cell in band row r0, and the line (relative to the tile) that
-// owns each of its 4 cells in that row (one more per ROWS rows down).
+// index of its first cell in band row r0, and the lines (relative to the
+// tile) that own its outer cells in that row (one more per ROWS rows down).
 struct BandGroup {
   uint32_t base;
   int lo, hi;  // smallest and largest owner: the owners of a group form a run of consecutive lines
@@ -748,12 +750,9 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
   const uint32_t NN = (uint32_t)N * (uint32_t)N;
   const int x0 = (tile % a.tiles_x) * LINES;
   const int T = as_global(a.planes)[tile / a.tiles_x];
-  // this plane's values (by byte offset for 16-byte access, by record for
-  // single cells) and codes (by byte offset)
+  // this plane's values and codes, addressed by byte offset
   const __amdgpu_buffer_rsrc_t rV =
       __builtin_amdgcn_make_buffer_rsrc(a.V + (size_t)T * NN, (short)0, (int)(NN * 4u), kBufferWord3);
-  const __amdgpu_buffer_rsrc_t bV =
-      __builtin_amdgcn_make_buffer_rsrc(a.V + (size_t)T * NN, (short)4, (int)NN, kBufferWord3);
   const __amdgpu_buffer_rsrc_t rB =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.B) + (size_t)T * NN, (short)0, (int)NN, kBufferWord3);
   const uint32_t Lq = as_global(a.edge_len)[T];
@@ -773,7 +772,6 @@ __device__ __forceinline__ void xmajor_band_tile(const SweepJob& a, int tile, XB
   const int r0 = tid / GW;  // first band row of this thread; rows r0 + it * ROWS
   const int gs = dir ? gw : GW - 1 - gw;  // the group's place in the band row (memory order)
   const int t_lim = (N - x0) < LINES ? (N - x0) : LINES;  // lines of this tile inside the grid
-  constexpr uint32_t kNoRecord = 0xFFFFFFFFu;
   constexpr uint32_t kNoOffset = 0xFFFFFFF0u;  // past the end of either plane: loads nothing
 
   // chunk k0 walks memory columns k0 .. k0 + nq - 1 (dir) or N - 1 - k0
