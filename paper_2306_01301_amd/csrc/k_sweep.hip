@@ -94,6 +94,16 @@ __device__ __forceinline__ RowBuffers row_buffers(const SweepJob& a) {
           __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.B), (short)1, (int)a.n_poses, kBufferWord3)};
 }
 
+// A job's tables are global memory; saying so lets the compiler read them
+// with global rather than generic loads (a job read from a batched job
+// table otherwise reaches them through generic pointers).
+template <typename T>
+using GlobalPtr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ GlobalPtr<T> as_global(T* p) {
+  return (GlobalPtr<T>)p;
+}
+
 // Workgroup index spread over the 8 XCDs so that consecutive tiles (which
 // share row segments at their edges) land on the same XCD and its L2.
 __device__ __forceinline__ int xcd_tile(int b, int n) {
@@ -418,8 +428,33 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
 // The workgroup has exactly one wave per section (64 S threads: the
 // launchers size it so); a workgroup of another size skips the tile.
 // POW2: N is a power of two.
+// A turn job's step geometry is the same in every tile of the job: the
+// plane, column offset and row offset of step s = threadIdx.x (a workgroup of
+// 64 S threads covers the S P steps, since P <= 64).  The kernels read it
+// once per job, so a turn tile's set-up reads no global memory and its loads
+// are issued while the previous tile's stores are still draining (a global
+// read there would first wait for every earlier store).
+struct TurnGeo {
+  uint32_t Tn;  // plane T times N
+  int shift;    // column offset of the curve through x' = 0
+  int oy;       // row offset of that curve from y'
+};
+template <int P>
+__device__ __forceinline__ TurnGeo turn_geo(const SweepJob& a) {
+  TurnGeo g{0u, 0, 0};
+  const int L = a.L, s = threadIdx.x;
+  if (a.cyclic && s < ((L + P - 1) / P) * P) {
+    const int sc = s < L ? s : L - 1;  // steps past the curve repeat the last one
+    const int T = a.dir ? sc : (L - 1 - sc);
+    g.Tn = (uint32_t)T * (uint32_t)a.N;
+    g.shift = as_global(a.offx)[T];
+    g.oy = as_global(a.offy)[T];
+  }
+  return g;
+}
+
 template <int P, bool FUSED, bool GUARD, bool POW2>
-__device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowShared& sh) {
+__device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowShared& sh, const TurnGeo& g) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int N = a.N, L = a.L;
@@ -435,12 +470,12 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
   int T0 = 0;
   uint32_t Lq = a.lq;
   int dir = a.dir;
-  const int16_t* sk = nullptr;
+  GlobalPtr<const int16_t> sk = nullptr;
   if (!cyclic) {
-    T0 = a.planes[outer];
-    Lq = a.edge_len[T0];
-    dir = (a.fwd[T0] > 0) == (a.mu_forward != 0);
-    sk = a.skew + (size_t)T0 * N;
+    T0 = as_global(a.planes)[outer];
+    Lq = as_global(a.edge_len)[T0];
+    dir = (as_global(a.fwd)[T0] > 0) == (a.mu_forward != 0);
+    sk = as_global(a.skew) + (size_t)T0 * N;
   }
   for (int c = threadIdx.x; c < 256; c += blockDim.x) {
     sh.wlut[c] = weight((uint32_t)c, 256u * Lq + 128u, 4u * Lq);
@@ -451,22 +486,24 @@ __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowS
   // The geometry of all steps goes to LDS once per workgroup.
   // Steps past the curve (the last section's tail when L is not a multiple
   // of P) repeat the geometry of the last step, so loads need no clamp.
-  for (int s = threadIdx.x; s < S * P; s += blockDim.x) {
-    int T, row, shift;
-    const int sc = s < L ? s : L - 1;
+  // (one step per thread: S P <= 64 S threads)
+  if (const int s = threadIdx.x; s < S * P) {
+    uint32_t Tn;
+    int row, shift;
     if (cyclic) {
-      T = dir ? sc : (L - 1 - sc);
-      shift = a.offx[T];
-      row = outer + a.offy[T];
+      Tn = g.Tn;
+      shift = g.shift;
+      row = outer + g.oy;
       row -= (row >= N) ? N : 0;
     } else {
-      T = T0;
+      Tn = (uint32_t)T0 * (uint32_t)N;
+      const int sc = s < L ? s : L - 1;
       const int c = dir ? sc : (L - 1 - sc);
       shift = sk[c];
       shift += (shift < 0) ? N : 0;
       row = c;
     }
-    const uint32_t rb = ((uint32_t)T * (uint32_t)N + (uint32_t)row) * (uint32_t)N;
+    const uint32_t rb = (Tn + (uint32_t)row) * (uint32_t)N;
     if (POW2) {
       sh.row_base[s] = rb | (uint32_t)shift;
     } else {
@@ -551,16 +588,16 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
   const int N = a.N;
   const uint32_t NN = (uint32_t)N * (uint32_t)N;
   const int x0 = (tile % a.tiles_x) * LINES;
-  const int T = a.planes[tile / a.tiles_x];
+  const int T = as_global(a.planes)[tile / a.tiles_x];
   // this plane's values and codes as record arrays indexed by row * N + column
   const __amdgpu_buffer_rsrc_t bV =
       __builtin_amdgcn_make_buffer_rsrc(a.V + (size_t)T * NN, (short)4, (int)NN, kBufferWord3);
   const __amdgpu_buffer_rsrc_t bB =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.B) + (size_t)T * NN, (short)1, (int)NN, kBufferWord3);
-  const uint32_t Lq = a.edge_len[T];
+  const uint32_t Lq = as_global(a.edge_len)[T];
   for (int c = tid; c < 256; c += NT) sh.wlut[c] = weight((uint32_t)c, 256u * Lq + 128u, 4u * Lq);
-  const int dir = (a.fwd[T] > 0) == (a.mu_forward != 0);
-  const int16_t* skg = a.skew + (size_t)T * N;
+  const int dir = (as_global(a.fwd)[T] > 0) == (a.mu_forward != 0);
+  const GlobalPtr<const int16_t> skg = as_global(a.skew) + (size_t)T * N;
   for (int c = tid; c < N; c += NT) sh.skew[c] = skg[c];
   __syncthreads();
   const int16_t* sk = sh.skew;
@@ -687,16 +724,6 @@ __device__ __forceinline__ void xmajor_sweep_tile(const SweepJob& a, int tile, X
 // are not stored.  PREF: the next chunk's band is loaded into registers while
 // the current one is scanned and stored, so each workgroup keeps loads in
 // flight through its whole loop.
-
-// A job's tables are global memory; saying so lets the compiler read them
-// with global rather than generic loads (a job read from a batched job
-// table otherwise reaches them through generic pointers).
-template <typename T>
-using GlobalPtr = __attribute__((address_space(1))) T*;
-template <typename T>
-__device__ __forceinline__ GlobalPtr<T> as_global(T* p) {
-  return (GlobalPtr<T>)p;
-}
 
 template <int Q_, int NT, int BUFS>
 struct XBand {
@@ -1042,9 +1069,10 @@ __device__ __forceinline__ int find_job(const SweepJob* __restrict__ jobs, int n
 template <int P, bool FUSED, bool GUARD, bool POW2>
 __global__ __launch_bounds__(1024) void row_sweep_kernel(SweepJob job) {
   __shared__ RowShared sh;
+  const TurnGeo g = turn_geo<P>(job);
   for (int b = blockIdx.x; b < job.blocks; b += gridDim.x) {
     __syncthreads();
-    row_sweep_tile<P, FUSED, GUARD, POW2>(job, tile_of(b, job.blocks, job.order), sh);
+    row_sweep_tile<P, FUSED, GUARD, POW2>(job, tile_of(b, job.blocks, job.order), sh, g);
   }
 }
 
@@ -1052,12 +1080,18 @@ template <int P, bool FUSED, bool GUARD, bool POW2>
 __global__ __launch_bounds__(1024) void row_sweep_batch_kernel(const SweepJob* __restrict__ jobs, int n_jobs,
                                                                  int total_blocks, int order) {
   __shared__ RowShared sh;
+  int jg = -1;  // job whose turn geometry g holds
+  TurnGeo g{0u, 0, 0};
   for (int b = blockIdx.x; b < total_blocks; b += gridDim.x) {
     __syncthreads();
     const int t = tile_of(b, total_blocks, order);
     const int j = __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, t));
     const SweepJob job = jobs[j];
-    row_sweep_tile<P, FUSED, GUARD, POW2>(job, t - job.first_block, sh);
+    if (j != jg) {
+      g = turn_geo<P>(job);
+      jg = j;
+    }
+    row_sweep_tile<P, FUSED, GUARD, POW2>(job, t - job.first_block, sh, g);
   }
 }
 
