@@ -407,7 +407,7 @@ def main() -> int:
     ap.add_argument("--skip-serving", action="store_true", help="skip the serving block")
     ap.add_argument("--skip-other", action="store_true", help="skip the parking_256 and plain_64 lines")
     ap.add_argument("--skip-check", action="store_true", help="skip the check against sweep_n_turns")
-    ap.add_argument("--serve-rates", default="20,200", help="serving block: Poisson rates in plans/s")
+    ap.add_argument("--serve-rates", default="20,100", help="serving block: Poisson rates in plans/s")
     ap.add_argument("--serve-requests", type=int, default=300, help="serving block: requests per rate")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="serving block: admission budget")
     ap.add_argument("--mode", default="batched", help="batch_64 workload: batched, continuous or single")
