@@ -198,20 +198,25 @@ def tick_plan(live: Sequence[_Live], now: float, fill_poses: int = FILL_POSES, t
 class Server:
     """Continuous batching over requests that arrive over time.
 
-    Three streams and an admission thread keep the GPU fed:
+    Three streams and two worker threads keep the GPU fed:
       * admission: arrived requests whose HBM footprint fits the budget are
         handed, most urgent first (the tick priority below), to a worker
         thread that makes their plans, uploads their images, renders their
         obstacle volumes and initialises their value volumes on its own
         stream, so neither this host work nor the synchronisations it needs
         hold up the sweeps (the library's calls release the interpreter
-        lock while they run);
+        lock while they run).  When no sweeps are running or queued there
+        is nothing to overlap, and the scheduling thread admits the requests
+        itself, sparing the hand-over;
       * sweeps: each tick, the plans tick_plan picks advance together in
         shared launches (batch_advance); at most MAX_QUEUED_TICKS ticks are
         enqueued ahead of the GPU;
-      * extraction: a plan whose last sweep has completed (its event) gets
-        its goal search and back-tracking here, with every other finished
-        plan, and releases its memory.
+      * extraction: the plans whose last sweeps a tick enqueues go at once
+        to a second worker thread, which enqueues their goal search and
+        back-tracking behind that tick's completion on the extraction
+        stream, waits for the result there and releases their plans, so the
+        extraction starts when the sweeps end and the scheduling thread
+        never waits for it.
     Requests that arrive meanwhile are admitted as memory and slots free."""
 
     def __init__(self, hbm_budget: int, max_live: int = 64, rule: str = "formula", digests: bool = False,
@@ -231,33 +236,79 @@ class Server:
         self.b_extract = P.Batch(max_live, stream=self.s_extract)
         self.peak_held = 0        # largest admitted footprint at once (bytes)
         self.admission_waits = 0  # ticks on which an arrived request waited for memory
+        self.admitted_inline = 0  # requests admitted by the scheduling thread (sweeps idle)
         self.ticks = 0
-        self.host_s = {"admit": 0.0, "tick": 0.0, "extract": 0.0, "wait": 0.0}  # main-thread host time per phase
+        self.host_s = {"admit": 0.0, "tick": 0.0, "wait": 0.0}  # scheduling-thread host time per phase
+
+    def _admit(self, job) -> tuple:
+        """Plans, images, rendering and init of requests [(k, scene, arrival,
+        footprint)] on the admission stream; returns (fresh plans, event)."""
+        fresh = []
+        with torch.cuda.stream(self.s_admit):
+            for k, sc, arrival, need in job:
+                pl = P.planner_for(sc, stream=self.s_admit)
+                img = torch.from_numpy(np.ascontiguousarray(sc.image)).cuda()
+                fresh.append(_Live(k, sc, pl, img, sc.n_cycles * len(sc.schedule), arrival, footprint=need))
+            planners = [f.planner for f in fresh]
+            self.b_admit.render(planners, [f.image for f in fresh], [f.scene.vehicle for f in fresh])
+            self.b_admit.init(planners, [f.scene.start for f in fresh])
+            ready = torch.cuda.Event()
+            ready.record(self.s_admit)
+        return fresh, ready
 
     def _admission(self, inbox: "queue.Queue", outbox: "queue.Queue") -> None:
-        """Worker thread: plans, images, rendering and init of handed-over requests."""
+        """Worker thread: admission of handed-over requests."""
         torch.cuda.set_device(self.device)
         while True:
             job = inbox.get()
             if job is None:
                 return
             try:
-                fresh = []
-                with torch.cuda.stream(self.s_admit):
-                    for k, sc, arrival, need in job:
-                        pl = P.planner_for(sc, stream=self.s_admit)
-                        img = torch.from_numpy(np.ascontiguousarray(sc.image)).cuda()
-                        fresh.append(_Live(k, sc, pl, img, sc.n_cycles * len(sc.schedule), arrival, footprint=need))
-                    planners = [f.planner for f in fresh]
-                    self.b_admit.render(planners, [f.image for f in fresh], [f.scene.vehicle for f in fresh])
-                    self.b_admit.init(planners, [f.scene.start for f in fresh])
-                    ready = torch.cuda.Event()
-                    ready.record(self.s_admit)
-                for f in fresh:
-                    f.finish_event = ready if f.total == 0 else None
-                outbox.put((fresh, ready))
+                outbox.put(self._admit(job))
             except BaseException as e:  # handed to the main thread, which raises it
                 outbox.put((e, None))
+
+    def _extraction(self, inbox: "queue.Queue", outbox: "queue.Queue", results: List[Result], t0: float) -> None:
+        """Worker thread: goal search and back-tracking of the plans whose
+        last sweeps one tick enqueued (handed over together with that tick's
+        event), then their release.  Posts the finished plans back."""
+        torch.cuda.set_device(self.device)
+        while True:
+            group = inbox.get()
+            if group is None:
+                return
+            try:
+                done, ev = group
+                self.s_extract.wait_event(ev)
+                for l in done:
+                    l.planner.set_stream(self.s_extract)  # its own work (digest, destroy) waits on this stream
+                if len(done) == 1:
+                    # one plan: extract_path, whose back-tracking spreads each step over one
+                    # workgroup per scheduled maneuver (a batch gives each plan one workgroup)
+                    l = done[0]
+                    try:
+                        paths = [l.planner.extract(l.scene.goal, l.scene.goal_radius, l.scene.w_xy,
+                                                   l.scene.w_t, cap=512)]
+                    except P.NhpError as e:
+                        paths = [e.rc]
+                else:
+                    paths = self.b_extract.extract([l.planner for l in done], [l.scene.goal for l in done],
+                                                   [l.scene.goal_radius for l in done],
+                                                   [l.scene.w_xy for l in done], [l.scene.w_t for l in done])
+                t = time.perf_counter() - t0
+                for l, path in zip(done, paths):
+                    r = results[l.k]
+                    r.finished = t
+                    if isinstance(path, int):
+                        r.status = path
+                    else:
+                        r.path = path
+                    if self.digests:
+                        r.value_digest = _digest(l.planner)
+                    l.planner.close()
+                outbox.put(done)
+            except BaseException as e:  # handed to the main thread, which raises it
+                outbox.put(e)
 
     def run(self, scs: Sequence, arrivals: Sequence[float]) -> List[Result]:
         import queue
@@ -267,20 +318,45 @@ class Server:
         pending = [int(k) for k in np.argsort(np.asarray(arrivals), kind="stable")]
         work = {k: sizing.pose_updates(scs[k].nx, scs[k].nt, scs[k].n_cycles, len(scs[k].schedule)) / UPDATE_RATE
                 for k in pending}
-        live: List[_Live] = []       # admitted and ready: sweeps still to enqueue or to complete
+        live: List[_Live] = []       # admitted and ready: sweeps still to enqueue, or extraction still to end
         admitting = 0                # handed to the admission thread, not back yet
+        extracting = 0               # plans handed to the extraction thread, not back yet
         queued: List[torch.cuda.Event] = []  # one per enqueued tick
         held = 0
         inbox, outbox = queue.Queue(), queue.Queue()
-        worker = threading.Thread(target=self._admission, args=(inbox, outbox), daemon=True)
-        worker.start()
+        x_in, x_out = queue.Queue(), queue.Queue()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         clock = time.perf_counter
+        worker = threading.Thread(target=self._admission, args=(inbox, outbox), daemon=True)
+        extractor = threading.Thread(target=self._extraction, args=(x_in, x_out, results, t0), daemon=True)
+        worker.start()
+        extractor.start()
+
+        def take(fresh, ready):
+            self.s_sweep.wait_event(ready)  # the sweeps of these plans come after their init
+            for f in fresh:
+                f.planner.set_stream(self.s_sweep)
+            live.extend(fresh)
+
         try:
             while pending or live or admitting:
                 now = clock() - t0
                 h0 = clock()
+                # ---- plans whose extraction has ended release their memory ----
+                freed = False
+                while True:
+                    try:
+                        done = x_out.get_nowait()
+                    except queue.Empty:
+                        break
+                    if isinstance(done, BaseException):
+                        raise done
+                    freed = True
+                    extracting -= len(done)
+                    held -= sum(l.footprint for l in done)
+                    gone = set(id(l) for l in done)
+                    live = [l for l in live if id(l) not in gone]
                 # ---- admission: arrived requests, most urgent first (expected
                 # work minus aging), memory and slots permitting ----
                 arrived = [k for k in pending if results[k].arrival <= now]
@@ -300,10 +376,17 @@ class Server:
                         self.peak_held = max(self.peak_held, held)
                         job.append((k, sc, results[k].arrival, need))
                         results[k].admitted = clock() - t0
-                if job:
-                    inbox.put(job)
-                    admitting += len(job)
+                queued = [e for e in queued if not e.query()]
                 got = False
+                if job:
+                    if not queued and admitting == 0 and all(l.done >= l.total for l in live):
+                        # no sweeps to overlap with: admit here, without the hand-over
+                        take(*self._admit(job))
+                        self.admitted_inline += len(job)
+                        got = True
+                    else:
+                        inbox.put(job)
+                        admitting += len(job)
                 while True:
                     try:
                         fresh, ready = outbox.get_nowait()
@@ -312,15 +395,11 @@ class Server:
                     if isinstance(fresh, BaseException):
                         raise fresh
                     got = True
-                    self.s_sweep.wait_event(ready)  # the sweeps of these plans come after their init
-                    for f in fresh:
-                        f.planner.set_stream(self.s_sweep)
-                    live.extend(fresh)
+                    take(fresh, ready)
                     admitting -= len(fresh)
                 h1 = clock()
                 self.host_s["admit"] += h1 - h0
                 # ---- one tick of sweeps ----
-                queued = [e for e in queued if not e.query()]
                 picked = tick_plan(live, now, self.fill_poses, self.tick_poses, self.aging) \
                     if len(queued) < MAX_QUEUED_TICKS else []
                 if picked:
@@ -330,15 +409,27 @@ class Server:
                     ev.record(self.s_sweep)
                     queued.append(ev)
                     self.ticks += 1
+                    finishing = []
                     for l, n in picked:
                         l.done += n
                         if l.done >= l.total:
-                            l.finish_event = ev
+                            finishing.append(l)
+                    if finishing:
+                        # extraction follows this tick on the extraction thread
+                        x_in.put((finishing, ev))
+                        extracting += len(finishing)
+                # plans admitted with no sweeps to run go straight to extraction
+                empty = [l for l in live if l.total == 0 and l.finish_event is None]
+                if empty:
+                    ev = torch.cuda.Event()
+                    ev.record(self.s_sweep)
+                    for l in empty:
+                        l.finish_event = ev
+                    x_in.put((empty, ev))
+                    extracting += len(empty)
                 h2 = clock()
                 self.host_s["tick"] += h2 - h1
-                # ---- extraction of plans whose sweeps have completed ----
-                done = [l for l in live if l.finish_event is not None and l.finish_event.query()]
-                if not done and not picked and not got and not job:
+                if not picked and not got and not job and not freed and not empty:
                     if queued:
                         queued[0].synchronize()  # nothing to do until the oldest enqueued tick completes
                     elif admitting:
@@ -346,47 +437,21 @@ class Server:
                             outbox.put(outbox.get(timeout=0.005))
                         except queue.Empty:
                             pass
+                    elif extracting:
+                        try:  # wait for the extraction thread
+                            x_out.put(x_out.get(timeout=0.005))
+                        except queue.Empty:
+                            pass
                     elif pending:
                         wait = min(results[k].arrival for k in pending) - (clock() - t0)
                         if wait > 0:
                             time.sleep(min(wait, 0.005))
                     self.host_s["wait"] += clock() - h2
-                    continue
-                if done:
-                    for l in done:
-                        self.s_extract.wait_event(l.finish_event)
-                        l.planner.set_stream(self.s_extract)  # its own work (digest, destroy) waits on this stream
-                    if len(done) == 1:
-                        # one plan: extract_path, whose back-tracking spreads each step over one
-                        # workgroup per scheduled maneuver (a batch gives each plan one workgroup)
-                        l = done[0]
-                        try:
-                            paths = [l.planner.extract(l.scene.goal, l.scene.goal_radius, l.scene.w_xy,
-                                                       l.scene.w_t, cap=512)]
-                        except P.NhpError as e:
-                            paths = [e.rc]
-                    else:
-                        paths = self.b_extract.extract([l.planner for l in done], [l.scene.goal for l in done],
-                                                       [l.scene.goal_radius for l in done],
-                                                       [l.scene.w_xy for l in done], [l.scene.w_t for l in done])
-                    t = clock() - t0
-                    for l, path in zip(done, paths):
-                        r = results[l.k]
-                        r.finished = t
-                        if isinstance(path, int):
-                            r.status = path
-                        else:
-                            r.path = path
-                        if self.digests:
-                            r.value_digest = _digest(l.planner)
-                        l.planner.close()
-                        held -= l.footprint
-                    gone = set(id(l) for l in done)
-                    live = [l for l in live if id(l) not in gone]
-                    self.host_s["extract"] += clock() - h2
         finally:
             inbox.put(None)
+            x_in.put(None)
             worker.join()
+            extractor.join()
         return results
 
     def close(self) -> None:
