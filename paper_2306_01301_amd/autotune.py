@@ -45,6 +45,28 @@ def _time_ms(fn, reps: int = 10) -> float:
     return s.elapsed_time(e) / reps
 
 
+def _time_on(pl, snapshot: torch.Tensor, fn, reps: int = 10) -> float:
+    """ms per call of fn, every call starting from the value volume
+    `snapshot` (restored before each call, outside the timed region).
+    Unchanged values are not stored, so a pass takes longer the more values
+    it changes; timing every setting from the same volume keeps the
+    comparison fair."""
+    st = pl.stream
+    evs = []
+    with torch.cuda.stream(st):
+        pl.value.copy_(snapshot)
+        fn()
+        for _ in range(reps):
+            pl.value.copy_(snapshot)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            fn()
+            b.record(st)
+            evs.append((a, b))
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in evs) / reps
+
+
 def candidates(length: int):
     return [p for p in (8, 16, 32, 64) if (length + p - 1) // p <= 16]
 
@@ -82,7 +104,8 @@ def set_knobs(values: dict) -> None:
 
 def measure_knobs(reps: int = 10) -> list:
     """ms of a fused turn pass plus a straight pass on a 512^3 and a 256^2 x
-    128 free-space volume for every knob setting of KNOB_GRID."""
+    128 free-space volume for every knob setting of KNOB_GRID, each timed
+    from the volume one cycle from the start leaves."""
     import itertools
 
     shapes = []
@@ -90,20 +113,21 @@ def measure_knobs(reps: int = 10) -> list:
         sc = scenes.free_space(nx, nt, max(1.0, nt / 8.0), 1).with_(ct=scenes.uniform_ct(8))
         pl = P.planner_for(sc)
         pl.render(torch.zeros((nx, nx), dtype=torch.uint8, device="cuda"), (1, 1, 1))
-        pl.sweep(sc.start, 0)
-        shapes.append(((nx, nt), pl))
+        pl.sweep(sc.start, 1)
+        shapes.append(((nx, nt), pl, pl.value.clone()))
     names = list(KNOB_GRID)
     rows = []
     for combo in itertools.product(*(KNOB_GRID[n] for n in names)):
         values = dict(zip(names, combo))
         set_knobs(values)
         ms = {}
-        for (nx, nt), pl in shapes:
-            ms["%dx%d" % (nx, nt)] = round(_time_ms(lambda: (pl.sweep_pass(P.RB, P.RF), pl.sweep_one(P.SF)), reps), 4)
+        for (nx, nt), pl, snap in shapes:
+            ms["%dx%d" % (nx, nt)] = round(
+                _time_on(pl, snap, lambda: (pl.sweep_pass(P.RB, P.RF), pl.sweep_one(P.SF)), reps), 4)
         rows.append({"knobs": values, "ms": ms})
         print("knobs %s: %s" % (values, ms), flush=True)
     set_knobs({n: 0 for n in names})
-    for _, pl in shapes:
+    for _, pl, _ in shapes:
         pl.close()
     return rows
 
