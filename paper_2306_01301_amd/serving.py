@@ -212,11 +212,10 @@ class Server:
         shared launches (batch_advance); at most MAX_QUEUED_TICKS ticks are
         enqueued ahead of the GPU;
       * extraction: the plans whose last sweeps a tick enqueues go at once
-        to a second worker thread, which enqueues their goal search and
-        back-tracking behind that tick's completion on the extraction
-        stream, waits for the result there and releases their plans, so the
-        extraction starts when the sweeps end and the scheduling thread
-        never waits for it.
+        to a second worker thread, which waits for that tick, runs their
+        goal search and back-tracking on the extraction stream and releases
+        their plans, so the scheduling thread never waits for an
+        extraction.
     Requests that arrive meanwhile are admitted as memory and slots free."""
 
     def __init__(self, hbm_budget: int, max_live: int = 64, rule: str = "formula", digests: bool = False,
@@ -268,7 +267,7 @@ class Server:
             except BaseException as e:  # handed to the main thread, which raises it
                 outbox.put((e, None))
 
-    def _extraction(self, inbox: "queue.Queue", outbox: "queue.Queue", results: List[Result], t0: float) -> None:
+    def _extraction(self, inbox: "queue.Queue", outbox: "queue.Queue", results: List[Result], t0: list) -> None:
         """Worker thread: goal search and back-tracking of the plans whose
         last sweeps one tick enqueued (handed over together with that tick's
         event), then their release.  Posts the finished plans back."""
@@ -295,7 +294,7 @@ class Server:
                     paths = self.b_extract.extract([l.planner for l in done], [l.scene.goal for l in done],
                                                    [l.scene.goal_radius for l in done],
                                                    [l.scene.w_xy for l in done], [l.scene.w_t for l in done])
-                t = time.perf_counter() - t0
+                t = time.perf_counter() - t0[0]
                 for l, path in zip(done, paths):
                     r = results[l.k]
                     r.finished = t
@@ -325,13 +324,14 @@ class Server:
         held = 0
         inbox, outbox = queue.Queue(), queue.Queue()
         x_in, x_out = queue.Queue(), queue.Queue()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        clock = time.perf_counter
+        t0_box = [0.0]  # the run's start, for the extraction thread's finish times
         worker = threading.Thread(target=self._admission, args=(inbox, outbox), daemon=True)
-        extractor = threading.Thread(target=self._extraction, args=(x_in, x_out, results, t0), daemon=True)
+        extractor = threading.Thread(target=self._extraction, args=(x_in, x_out, results, t0_box), daemon=True)
         worker.start()
         extractor.start()
+        torch.cuda.synchronize()
+        t0 = t0_box[0] = time.perf_counter()
+        clock = time.perf_counter
 
         def take(fresh, ready):
             self.s_sweep.wait_event(ready)  # the sweeps of these plans come after their init
