@@ -353,7 +353,9 @@ int nhp_set_section_steps(uint32_t curve_len, uint32_t steps);
  * the launches they captured. */
 enum nhp_knob {
   NHP_KNOB_ROW_WG_PER_CU = 0,    /* workgroups per compute unit that the row sweep launches keep resident, 1..8 */
-  NHP_KNOB_XMAJOR_WG_PER_CU = 1, /* the same for the x-major straight launches, 1..16 */
+  NHP_KNOB_XMAJOR_WG_PER_CU = 1, /* workgroups per compute unit in the grid of the x-major straight launches,
+                                    1..16; built-in: 16 for grids of at least 32 cells (one workgroup per tile
+                                    up to 4096 tiles, 5 resident per compute unit), 6 below */
   NHP_KNOB_TILE_ORDER = 2,       /* 1: tiles that share row segments run on one XCD (its L2); 2: launch order */
   NHP_KNOB_XMAJOR_BUFFERS = 3    /* x-major LDS tiles per workgroup: 2 (the next chunk's loads need no barrier
                                     after the stores) or 1 (more workgroups fit a compute unit); built-in: 1 for

@@ -71,10 +71,10 @@ def _oracle_key(sc):
 
 def test_served_results_match_oracle():
     """Small and large requests (a 512-side request among them) admitted
-    under a budget that makes requests wait, with ticks small enough that
-    plans are picked in turn (shortest remaining work first) and share
-    launches at different points of their schedules: every served result
-    equals the oracle's."""
+    under a budget that makes requests wait, by both admission paths, with
+    ticks small enough that plans are picked in turn (shortest remaining
+    work first) and share launches at different points of their schedules:
+    every served result equals the oracle's."""
     import os
 
     import oracle
@@ -91,6 +91,9 @@ def test_served_results_match_oracle():
     served = srv.run(reqs, arrivals)
     srv.close()
     assert srv.admission_waits > 0 and srv.ticks > len(reqs)
+    # both admission paths ran: by the scheduling thread while no sweeps were
+    # queued (the first requests), by the admission thread behind running sweeps
+    assert 0 < srv.admitted_inline < len(reqs)
     for sc, r in zip(reqs, served):
         print("request %s %dx%dx%d N=%d: oracle" % (sc.name, sc.nx, sc.nx, sc.nt, sc.n_cycles), flush=True)
         assert _key(r) == _oracle_key(sc), sc.name
