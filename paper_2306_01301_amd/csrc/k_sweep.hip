@@ -418,16 +418,6 @@ __device__ __forceinline__ void scan_section_wide(const SweepJob& a, const RowBu
   }
 }
 
-// Row-coalesced sweep of one tile (64 curves) of a job: turns (cyclic) and
-// y-major straights.
-//   turns:     tile -> (x tile, y'); step k -> plane T_k, offsets (ox, oy)
-//   straights: tile -> (x tile, plane slot); step k -> row c_k, column x' + B(c_k)
-// FUSED (turns): after the first maneuver the second one, on the same curves
-// in the opposite direction, runs on the values still held in registers, so
-// the pair costs one read and one write per pose.
-// The workgroup has exactly one wave per section (64 S threads: the
-// launchers size it so); a workgroup of another size skips the tile.
-// POW2: N is a power of two.
 // A turn job's step geometry is the same in every tile of the job: the
 // plane, column offset and row offset of step s = threadIdx.x (a workgroup of
 // 64 S threads covers the S P steps, since P <= 64).  The kernels read it
@@ -453,6 +443,16 @@ __device__ __forceinline__ TurnGeo turn_geo(const SweepJob& a) {
   return g;
 }
 
+// Row-coalesced sweep of one tile (64 curves) of a job: turns (cyclic) and
+// y-major straights.
+//   turns:     tile -> (x tile, y'); step k -> plane T_k, offsets (ox, oy)
+//   straights: tile -> (x tile, plane slot); step k -> row c_k, column x' + B(c_k)
+// FUSED (turns): after the first maneuver the second one, on the same curves
+// in the opposite direction, runs on the values still held in registers, so
+// the pair costs one read and one write per pose.
+// The workgroup has exactly one wave per section (64 S threads: the
+// launchers size it so); a workgroup of another size skips the tile.
+// POW2: N is a power of two.  g: the job's turn geometry (turn_geo).
 template <int P, bool FUSED, bool GUARD, bool POW2>
 __device__ __forceinline__ void row_sweep_tile(const SweepJob& a, int tile, RowShared& sh, const TurnGeo& g) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
