@@ -424,20 +424,30 @@ __device__ __forceinline__ void extract_body(const ExArgs& x, uint32_t (*red32)[
         status = (uint32_t)(-NHP_EHIP);
         break;
       }
-      best = ~0ull;
-      int from = 0;
-      for (int g = 0; g < (int)gridDim.x; g++) {
-        const uint32_t* e = sync + 1 + ((iter & 1) * 6 + g) * 4;
-        const uint64_t kg = (uint64_t)load_shared_word(e) | ((uint64_t)load_shared_word(e + 1) << 32);
-        if (kg < best) {
-          best = kg;
-          from = g;
-        }
+      // the four words of all 6 slots read in one round (the area always
+      // holds 6; slots past the grid are read and ignored), then the best
+      // of the grid's workgroups taken
+      uint32_t ex[6][4];
+      const uint32_t* slots = sync + 1 + (iter & 1) * 6 * 4;
+#pragma unroll
+      for (int g = 0; g < 6; g++) {
+#pragma unroll
+        for (int m = 0; m < 4; m++) ex[g][m] = load_shared_word(slots + g * 4 + m);
       }
-      if (best != ~0ull) {
-        const uint32_t* e = sync + 1 + ((iter & 1) * 6 + from) * 4;
-        vnext = load_shared_word(e + 2);
-        cost = load_shared_word(e + 3);
+#pragma unroll
+      for (int g = 0; g < 6; g++)
+        asm volatile("" : "+v"(ex[g][0]), "+v"(ex[g][1]), "+v"(ex[g][2]), "+v"(ex[g][3]));  // all arrived first
+      best = ~0ull;
+#pragma unroll
+      for (int g = 0; g < 6; g++) {
+        if (g < (int)gridDim.x) {
+          const uint64_t kg = (uint64_t)ex[g][0] | ((uint64_t)ex[g][1] << 32);
+          if (kg < best) {
+            best = kg;
+            vnext = ex[g][2];
+            cost = ex[g][3];
+          }
+        }
       }
     }
     if (best == ~0ull) {
