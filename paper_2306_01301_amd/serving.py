@@ -149,7 +149,7 @@ class _Live:
     arrival: float
     done: int = 0           # sweeps enqueued so far
     footprint: int = 0
-    finish_event: Optional[torch.cuda.Event] = None
+    finish_event: Optional[torch.cuda.Event] = None  # a plan with no sweeps: the event it was handed over with
 
     @property
     def remaining_updates(self) -> int:
