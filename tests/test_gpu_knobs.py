@@ -19,6 +19,9 @@ SETTINGS = [
     {"row_wg_per_cu": 1, "xmajor_wg_per_cu": 4, "tile_order": 2, "xmajor_buffers": 1},
     {"row_wg_per_cu": 2, "xmajor_wg_per_cu": 16, "tile_order": 1, "xmajor_buffers": 2},
     {"xmajor_buffers": 1},
+    # one x-major workgroup per CU: band tiles walk several tiles each (the
+    # dirty-row flags and their chunk parity carry across tiles)
+    {"xmajor_wg_per_cu": 1},
 ]
 
 
@@ -34,7 +37,7 @@ def _gpu():
     P.apply_tuning()
 
 
-@pytest.mark.parametrize("N,L,R", [(200, 72, 7.5), (512, 40, 20.0), (64, 256, 10.0)])
+@pytest.mark.parametrize("N,L,R", [(200, 72, 7.5), (512, 40, 20.0), (64, 256, 10.0), (512, 128, 16.0)])
 @pytest.mark.parametrize("setting", range(len(SETTINGS)))
 def test_every_knob_setting_matches_oracle(N, L, R, setting):
     for name in P.KNOBS:
